@@ -1,0 +1,18 @@
+"""Seeded synthetic inputs shared by the oracle tests and the GPU path.
+
+This package only describes workloads (grid and scan parameters) and draws
+phantoms and their analytic projections.  It holds none of the reconstruction
+method's arithmetic (no grid tracing, no MART): both the CPU oracle and the
+HIP library consume the arrays it writes, so it must not depend on either.
+"""
+
+from .workloads import (  # noqa: F401
+    Workload, WORKLOADS, get, small_cone, cone, parallel, batch2d_members, serve_request,
+)
+from .phantoms import (  # noqa: F401
+    draw_phantom,
+    scan_rays,
+    project,
+    add_noise,
+    make_projections,
+)

@@ -1,0 +1,139 @@
+"""Workload descriptions: grid, scan geometry, phantom recipe and solver settings.
+
+Every workload is a plain record.  Geometry conventions (the readings of the
+paper's problem statement that the oracle and the library both follow):
+
+* The reconstruction domain is a disk (2D) or a cylinder (3D) of radius R
+  centred on the z axis; a cylinder spans z in [-H/2, H/2] with H = 2R.
+* Rings have equal radial spacing r = R / n_rings (Sec. II.A).  With the
+  ``multiple`` sector rule ring i (0-based) holds m * ceil(2*pi*(i+1/2)/m)
+  sectors, so every cell has area close to r^2 and every ring's sector count is
+  a multiple of m; with the ``paper`` rule ring i holds 4(2i+1) sectors (eq. 1).
+* View v sits at angle v * span / n_views, anticlockwise about z.
+* parallel2d: view-0 ray b is the line y = t_b, t_b = -W + (b+1/2) 2W/B.
+* fan2d / cone3d: view-0 source at (-D_so, 0, 0), flat detector at
+  x = D_sd - D_so; detector pixel (u, w) has centre
+  (D_sd - D_so, -W_u + (u+1/2) 2W_u/U, -W_v + (w+1/2) 2W_v/V), ray index
+  r = w * U + u.  The detector bounds the cylinder's shadow:
+  W_u = D_sd R / sqrt(D_so^2 - R^2) and W_v = D_sd (H/2) / (D_so - R).
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import Optional
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    geometry: str                 # "parallel2d" | "fan2d" | "cone3d"
+    n_rings: int
+    n_slices: int = 1
+    radius: float = 1.0
+    height: float = 0.0           # cylinder height (3D); 0 for 2D
+    sector_rule: str = "multiple"  # "paper" | "multiple" | "explicit"
+    sector_multiple: int = 8
+    n_views: int = 8
+    span: float = math.pi
+    det_u: int = 64
+    det_v: int = 1
+    det_half_u: float = 1.0
+    det_half_v: float = 0.0
+    src_axis: float = 0.0
+    src_det: float = 0.0
+    binary: bool = False
+    phantom: str = "ellipses"     # "ellipses" | "ellipsoids" | "body_inclusions" | "none"
+    n_objects: int = 6
+    seed: int = 1
+    noise: float = 0.01
+    sweeps: int = 10
+    beta: float = 0.1
+    dtype: str = "f32"
+    remap_nc: int = 0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_rays(self) -> int:
+        return self.det_u * self.det_v
+
+    @property
+    def is3d(self) -> bool:
+        return self.geometry == "cone3d"
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+
+def cone(name: str, n_rings: int, n_views: int, det: int, m: int, **kw) -> Workload:
+    """Cone-beam USCG workload with the fixed geometry ratios
+    (source-to-axis 4R, source-to-detector 8R, cylinder height 2R)."""
+    R, H, dso, dsd = 1.0, 2.0, 4.0, 8.0
+    return Workload(
+        name=name, geometry="cone3d", n_rings=n_rings, n_slices=kw.pop("n_slices", n_rings),
+        radius=R, height=H, sector_rule="multiple", sector_multiple=m,
+        n_views=n_views, span=2 * math.pi, det_u=det, det_v=det,
+        det_half_u=dsd * R / math.sqrt(dso * dso - R * R),
+        det_half_v=dsd * (H / 2) / (dso - R),
+        src_axis=dso, src_det=dsd, **kw)
+
+
+def parallel(name: str, n_rings: int, n_views: int, bins: int, m: int, **kw) -> Workload:
+    """2D parallel-beam USPG workload over a half turn; bins span the diameter."""
+    return Workload(
+        name=name, geometry="parallel2d", n_rings=n_rings, n_slices=1, radius=1.0,
+        sector_rule="multiple", sector_multiple=m, n_views=n_views, span=math.pi,
+        det_u=bins, det_v=1, det_half_u=1.0, **kw)
+
+
+WORKLOADS = {
+    # 2D parallel beam, FP64 plain MART: 32 rings, 8 views over 180 degrees, 64 bins.
+    # Sector counts are multiples of 16 so that the 22.5-degree view step is a
+    # whole number of sectors in every ring.
+    "par2d-32r-8v": parallel("par2d-32r-8v", 32, 8, 64, 16, phantom="ellipses",
+                             n_objects=6, seed=1, sweeps=10, beta=0.1, dtype="f64"),
+    # 3D cone beam USCG, FP32: 128 rings x 128 slices, 16 views, 256x256 detector.
+    "cone-128r-16v": cone("cone-128r-16v", 128, 16, 256, 16, phantom="ellipsoids",
+                          n_objects=10, seed=2, sweeps=20, beta=0.1, dtype="f32"),
+    # 3D cone beam USCG, FP32, high contrast: 256 rings x 256 slices, 32 views,
+    # 512x512 detector, body ellipsoid with 3 dense inclusions, then a remap to
+    # a 512 x 512 x 256 Cartesian grid.
+    "cone-256r-32v-hc": cone("cone-256r-32v-hc", 256, 32, 512, 32, phantom="body_inclusions",
+                             n_objects=4, seed=3, sweeps=20, beta=0.05, dtype="f32",
+                             remap_nc=512),
+}
+
+
+def batch2d_members(n: int = 64, seed: int = 4) -> list:
+    """The many-slice 2D workload: ring counts from {32,64,128,256}, views
+    from {8,16,32}, 2*Nr bins, sector multiple 2p (half-turn scan), 15 sweeps."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        nr = int(rng.choice([32, 64, 128, 256]))
+        p = int(rng.choice([8, 16, 32]))
+        out.append(parallel(f"batch2d-{k}", nr, p, 2 * nr, 2 * p, phantom="ellipses",
+                            n_objects=6, seed=4000 + k, sweeps=15, beta=0.1, dtype="f32"))
+    return out
+
+
+def serve_request(k: int, nr: int, p: int, sweeps: int) -> Workload:
+    """One request of the serving workload: cone-beam USCG, Nr = Nz, detector
+    2Nr x 2Nr, sector multiple p, random ellipsoid phantom."""
+    return cone(f"serve-{k}", nr, p, 2 * nr, p, phantom="ellipsoids", n_objects=10,
+                seed=5000 + k, sweeps=sweeps, beta=0.1, dtype="f32")
+
+
+def get(name: str) -> Workload:
+    return WORKLOADS[name]
+
+
+def small_cone(name: str = "cone-16r-8v", n_rings: int = 16, n_views: int = 8, det: int = 32,
+               m: Optional[int] = None, **kw) -> Workload:
+    """Scaled-down cone-beam workload with the same ratios, for fast tests."""
+    return cone(name, n_rings, n_views, det, m if m is not None else n_views,
+                phantom=kw.pop("phantom", "ellipsoids"), n_objects=kw.pop("n_objects", 10),
+                seed=kw.pop("seed", 7), sweeps=kw.pop("sweeps", 5), beta=kw.pop("beta", 0.1),
+                dtype=kw.pop("dtype", "f32"), **kw)
