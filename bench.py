@@ -1,0 +1,148 @@
+#!/usr/bin/env python3
+"""Throughput of MART on the 256-ring cone-beam USCG (high-contrast phantom).
+
+One step = the whole path on one synthetic input already resident in HBM:
+grid build, reference-view trace + colouring, 20 MART sweeps over 32 views,
+and the remap to a 512 x 512 x 256 Cartesian grid.  Prints one JSON line.
+
+value = MART ray-cell updates per second of the whole step
+        (views * reference nonzeros * sweeps / step time).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cone-256r-32v-hc")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=12, help="detector rows in the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, lattice, P, rows):
+    """The FP64 oracle on a bounded sample of the same workload: the rays of
+    `rows` central detector rows, traced, then MART over all views and sweeps
+    with every other row empty."""
+    from oracle import Oracle
+    from oracle.oracle import CSR
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = Oracle(w, nthreads=threads)
+    V, U = w.det_v, w.det_u
+    w0 = V // 2 - rows // 2
+    rays = [wv * U + u for wv in range(w0, w0 + rows) for u in range(U)]
+    t0 = time.perf_counter()
+    counts = np.zeros(o.n_rays, dtype=np.int64)
+    cells, lens = [], []
+    for r in rays:
+        S, D = o.ray(0, r)
+        c, l = o.trace_line(S, D)
+        counts[r] = len(c)
+        cells.append(c)
+        lens.append(l)
+    rowptr = np.concatenate([[0], np.cumsum(counts)])
+    order = np.argsort(rays)
+    csr = CSR(rowptr, np.concatenate([cells[i] for i in order]), np.concatenate([lens[i] for i in order]))
+    t1 = time.perf_counter()
+    o.mart(csr, lattice, P, np.ones(o.n_cells), w.sweeps, w.beta)
+    t2 = time.perf_counter()
+    updates = w.n_views * csr.nnz * w.sweeps
+    return {"value": updates / (t2 - t0), "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rows} central detector rows ({len(rays)} rays, {csr.nnz} reference nonzeros) of "
+                      f"{w.name}: trace {t1 - t0:.2f} s + {w.sweeps} MART sweeps over {w.n_views} views "
+                      f"{t2 - t1:.2f} s, FP64"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(independent reconstructions shard with no communication; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2208_12964_amd as U
+    import synth
+
+    w = synth.get(args.workload)
+    dev = torch.device("cuda:0")
+    P = synth.make_projections(w)
+    proj = torch.as_tensor(P, dtype=torch.float32).to(dev).contiguous()
+    nc = w.remap_nc or 2 * w.n_rings
+    stream = torch.cuda.current_stream()
+
+    def step(record=None):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        grid = U.Grid.from_workload(w)
+        co = U.Coeffs.from_workload(grid, w, torch.float32)
+        ev[1].record(stream)
+        img = torch.ones(grid.n_cells, dtype=torch.float32, device=dev)
+        U.mart(co, proj, img, w.sweeps, w.beta)
+        ev[2].record(stream)
+        cart = U.to_cartesian(grid, img, nc)
+        ev[3].record(stream)
+        if record is not None:
+            record.append((ev, co.nnz, co.lattice, co.max_row))
+        return img, cart, co, grid
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        img, cart, co, grid = step(rec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    nnz, lattice = rec[0][1], rec[0][2]
+    updates = w.n_views * nnz * w.sweeps
+    build_ms = np.mean([r[0][0].elapsed_time(r[0][1]) for r in rec])
+    mart_ms = np.mean([r[0][1].elapsed_time(r[0][2]) for r in rec])
+    remap_ms = np.mean([r[0][2].elapsed_time(r[0][3]) for r in rec])
+    n_launch = w.sweeps * w.n_views * lattice[0] * lattice[1]
+    per_launch_s = mart_ms * 1e-3 / n_launch
+    bytes_per_launch = 16.0 * updates / n_launch
+    achieved = bytes_per_launch / per_launch_s / 1e9
+    f = img.float().cpu().numpy()
+    out = {
+        "metric": "MART ray-cell updates/s", "value": updates / (ms_step * 1e-3), "unit": "updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "rings": w.n_rings, "slices": w.n_slices, "views": w.n_views,
+                   "detector": f"{w.det_u}x{w.det_v}", "sweeps": w.sweeps, "beta": w.beta,
+                   "nnz_ref": nnz, "lattice": list(lattice), "remap": f"{nc}x{nc}x{w.n_slices}"},
+        "sweeps_per_s": w.sweeps / (mart_ms * 1e-3),
+        "phases_ms": {"build": build_ms, "mart": mart_ms, "remap": remap_ms},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "mart_batch", "bytes_per_update": 16,
+                     "launches_per_step": n_launch, "avg_launch_us": per_launch_s * 1e6},
+        "image": {"min": float(f.min()), "max": float(f.max())},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, lattice, P, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

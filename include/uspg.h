@@ -1,0 +1,197 @@
+/*
+ * uspg.h -- C ABI of the MI355X (gfx950) library for MART reconstruction on a
+ * Uniformly Sampled Polar / Cylindrical Grid (USPG in 2D, USCG in 3D).
+ *
+ * Method: Chaudhary, Wahi, Munshi, "Uniformly Sampled Polar and Cylindrical
+ * Grid Approach for 2D, 3D Image Reconstruction using Algebraic Algorithm".
+ * Coefficients are traced for the first (reference) view only and reused for
+ * every other view by rotating the angular cell index (Sec. III.B-C); the
+ * image is solved with Sp-MART (Sec. III.D) and mapped to a Cartesian grid for
+ * display (Sec. II.B).
+ *
+ * Conventions shared by every call:
+ *  - Every entry point returns USPG_OK (0) or a negative status; no call
+ *    aborts or throws.  uspg_last_error() gives a message for the calling
+ *    thread's last failure.
+ *  - Handles (uspg_grid, uspg_coeffs) are opaque host objects owned by the
+ *    library and released with the matching uspg_free_* call.  A handle is
+ *    bound to the HIP device that was current when it was built and must be
+ *    used with that device current.  Handles are immutable after the build
+ *    and may be shared by calls on different streams.
+ *  - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued on it asynchronously unless a call says
+ *    otherwise.
+ *  - Device buffers passed in (projections, images, work space, Cartesian
+ *    output) are owned by the caller and must be device-accessible memory on
+ *    the handle's device.  The library owns the device memory inside handles.
+ *  - Images are in the paper's numbering: cell (slice k, ring i, sector s) has
+ *    index k * C2D + H_i + s, with H_i the ring head (eq. 2), rings 0-based
+ *    from the centre and sectors anticlockwise from the +x axis.
+ */
+#ifndef USPG_H
+#define USPG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define USPG_OK 0
+#define USPG_E_ARG (-1)      /* invalid argument (null, size, range, dtype)       */
+#define USPG_E_SHIFT (-2)    /* views are not a whole number of sectors per ring  */
+#define USPG_E_NOMEM (-3)    /* device allocation failed or work space too small  */
+#define USPG_E_HIP (-4)      /* HIP runtime error (reported at this or a later call) */
+#define USPG_E_INTERNAL (-5) /* internal consistency check failed                 */
+
+/* ---- enumerations ------------------------------------------------------- */
+enum {
+    USPG_SECTORS_PAPER = 0,    /* ring n (1-based) has 4(2n-1) sectors (eq. 1)          */
+    USPG_SECTORS_MULTIPLE = 1, /* ring i (0-based) has m * ceil(2 pi (i + 1/2) / m)      */
+    USPG_SECTORS_EXPLICIT = 2  /* caller's table                                         */
+};
+enum {
+    USPG_PARALLEL_2D = 0, /* view-0 ray b is the line y = -W + (b + 1/2) 2W / B             */
+    USPG_FAN_2D = 1,      /* point source (-D_so, 0), flat detector at x = D_sd - D_so      */
+    USPG_CONE_3D = 2      /* point source (-D_so, 0, 0), flat U x V detector at x = D_sd - D_so */
+};
+enum { USPG_WEIGHTS_LENGTH = 0, USPG_WEIGHTS_BINARY = 1 };
+enum { USPG_F32 = 0, USPG_F64 = 1 };
+enum { USPG_REMAP_POINT = 0, USPG_REMAP_BIJECTION = 1 };
+
+typedef struct uspg_grid uspg_grid;
+typedef struct uspg_coeffs uspg_coeffs;
+
+/* ---- grid (Sec. II.A, eqs. 1-2; Sec. III.A USCG) --------------------------
+ * A disk (n_slices == 1) or a cylinder of radius `radius` and height `height`
+ * centred on the origin, cut into n_rings rings of equal spacing
+ * r = radius / n_rings, each ring into sectors (rule below) and, in 3D, into
+ * n_slices slices of thickness height / n_slices.  `sectors` is read only for
+ * USPG_SECTORS_EXPLICIT (n_rings host entries, each >= 2).  The rule must give
+ * every ring enough sectors that a line cannot dip two rings deep inside one
+ * sector (true for the paper and multiple rules); otherwise USPG_E_ARG. */
+typedef struct {
+    int32_t n_rings;
+    int32_t n_slices;       /* 1 for a 2D disk */
+    double radius;
+    double height;          /* ignored when n_slices == 1 */
+    int32_t sector_rule;
+    int32_t sector_multiple;
+    const int32_t *sectors;
+} uspg_grid_desc;
+
+/* Builds the grid tables on the host and uploads them to the current device
+ * (synchronous).  *out receives the handle. */
+int uspg_build_grid(const uspg_grid_desc *desc, uspg_grid **out);
+
+/* Sizes of a grid.  Any output pointer may be NULL. */
+int uspg_grid_info(const uspg_grid *g, int64_t *n_cells, int64_t *cells_per_slice,
+                   int32_t *n_rings, int32_t *n_slices);
+
+/* Host copies of the per-ring sector counts (n_rings entries) and heads
+ * (n_rings + 1 entries, heads[n_rings] = cells per slice).  NULL skips. */
+int uspg_grid_tables(const uspg_grid *g, int32_t *sectors, int64_t *heads);
+
+void uspg_free_grid(uspg_grid *g);
+
+/* ---- scan and coefficients (Sec. III.A-C, Alg. 1) ------------------------
+ * View v is the view-0 arrangement rotated anticlockwise about z by
+ * v * span / n_views.  q = n_views * 2 pi / span must be an integer that
+ * divides every ring's sector count, so that a view step is a whole number of
+ * sectors in every ring; otherwise USPG_E_SHIFT.
+ * Detector: det_u columns x det_v rows (det_v = 1 in 2D), ray index
+ * r = w * det_u + u, pixel centres at -W + (j + 1/2) 2W / count with
+ * W = det_half_u (columns) or det_half_v (rows).  Parallel 2D uses only
+ * det_u and det_half_u.  src_axis = D_so, src_det = D_sd.
+ * weights: LENGTH stores the intersection length of ray and cell, BINARY
+ * stores 1 for every traversed cell (Sec. III.B).
+ * coeff_dtype: storage of the coefficients (USPG_F32 or USPG_F64).
+ * colour_u, colour_v: 0 = choose the smallest valid lattice; otherwise the
+ * lattice is checked and USPG_E_ARG is returned if two rays of one class
+ * share a cell. */
+typedef struct {
+    int32_t geometry;
+    int32_t n_views;
+    double span;
+    int32_t det_u, det_v;
+    double det_half_u, det_half_v;
+    double src_axis, src_det;
+    int32_t weights;
+    int32_t coeff_dtype;
+    int32_t colour_u, colour_v;
+} uspg_scan_desc;
+
+/* Traces every view-0 ray through the grid on the device (FP64 geometry),
+ * stores the reference rows (one entry per traversed cell, duplicates merged)
+ * and colours the rays into cell-disjoint lattice classes.  Allocates the
+ * handle's device memory with hipMalloc; synchronises `stream` once (to size
+ * the rows).  The grid must outlive the coefficients. */
+int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *scan, void *stream,
+                      uspg_coeffs **out);
+
+/* Sizes of the reference rows and the chosen lattice (classes are
+ * c = (w mod colour_v) * colour_u + (u mod colour_u)).  NULL skips. */
+int uspg_coeffs_info(const uspg_coeffs *c, int64_t *nnz_ref, int64_t *n_rays,
+                     int32_t *colour_u, int32_t *colour_v, int32_t *max_row,
+                     int64_t *device_bytes);
+
+/* Host copy of the row of ray `ray` in view `view` (cells in the paper's
+ * numbering, rotated to that view; lengths as stored).  Synchronous; for
+ * inspection and tests.  *n receives the row length; USPG_E_NOMEM if it
+ * exceeds cap (nothing written). */
+int uspg_coeffs_row(const uspg_coeffs *c, int32_t view, int64_t ray, int64_t *cells,
+                    double *lengths, int32_t cap, int32_t *n);
+
+/* Host copy of the conflict-offset map used by the colouring:
+ * mark[dw * det_u + du] = 1 when two view-0 rays whose detector indices
+ * differ by (du, dw) share a cell.  mark has det_u * det_v bytes. */
+int uspg_coeffs_conflicts(const uspg_coeffs *c, uint8_t *mark);
+
+void uspg_free_coeffs(uspg_coeffs *c);
+
+/* ---- MART (Sec. III.D, eqs. 17-19) ---------------------------------------
+ * For each sweep, for each view v ascending, for each lattice class c
+ * ascending, every ray r of the class is applied (the rays of a class share no
+ * cell, so applying them together equals applying them one by one):
+ *   Pbar = sum_j a_rj f_j                     (eq. 17, rotated row of view v)
+ *   f_j <- f_j (1 - beta (a_rj / a_max,r) (1 - P[v][r] / Pbar))   (eq. 18)
+ * Rays with an empty row or Pbar <= 0 are skipped.  With binary weights this
+ * is eq. 18 exactly.  beta > 0; positivity of f is kept for beta <= 1.
+ * dtype: USPG_F32 or USPG_F64 for proj, image and the arithmetic.
+ * proj:  device [n_views][det_v][det_u], non-negative.
+ * image: device [n_cells] in the paper's numbering; read as f0 (> 0) and
+ *        overwritten with the result.
+ * work:  device scratch of at least uspg_mart_workspace_bytes() bytes.
+ * tol:   0 runs exactly n_sweeps sweeps with no host synchronisation; tol > 0
+ *        stops after the first sweep with max_j |f_new - f_old| / f_old <= tol
+ *        (eq. 19) and synchronises the stream once per sweep.
+ * sweeps_done: host, nullable; receives the number of sweeps run (written
+ *        before return, so only meaningful after the stream is synchronised
+ *        when tol == 0 -- it is then simply n_sweeps). */
+size_t uspg_mart_workspace_bytes(const uspg_coeffs *c, int32_t dtype, double tol);
+
+int mart_run(const uspg_coeffs *c, int32_t dtype, const void *proj, void *image, void *work,
+             size_t work_bytes, int32_t n_sweeps, double beta, double tol,
+             int32_t *sweeps_done, void *stream);
+
+/* ---- USPG -> Cartesian grid (Sec. II.B) -----------------------------------
+ * cart: device [n_slices][nc][nc]; pixel (ix, iy) covers the square of side
+ * 2R/nc centred at ((2 ix + 1 - nc) R / nc, (2 iy + 1 - nc) R / nc).
+ * POINT: the pixel takes the value of the cell containing its centre (0
+ *   outside the disk); centres on a diagonal use the exact angle.
+ * BIJECTION: paper grid only (sector rule PAPER) with nc = 2 n_rings: square
+ *   ring n (pixels with max(|2ix+1-nc|, |2iy+1-nc|) = 2n - 1) and circular
+ *   ring n hold the same number of cells and are matched one to one, both
+ *   numbered anticlockwise from the +x axis. */
+int uspg_to_cartesian(const uspg_grid *g, int32_t dtype, const void *image, void *cart,
+                      int32_t nc, int32_t mode, void *stream);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *uspg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* USPG_H */

@@ -1,0 +1,256 @@
+"""Python binding of libuspg (MART on a uniformly sampled polar / cylindrical
+grid, HIP on gfx950).
+
+Thin ctypes marshalling over the C ABI in ``include/uspg.h``: every step of
+the computation runs in the library's kernels.  Torch tensors are used only as
+device memory and for the current stream.  Loading fails loudly if the
+library has not been built (``python paper_2208_12964_amd/build.py``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libuspg.so")
+
+# enumerations (mirror include/uspg.h)
+SECTORS = {"paper": 0, "multiple": 1, "explicit": 2}
+GEOMETRY = {"parallel2d": 0, "fan2d": 1, "cone3d": 2}
+WEIGHTS = {"length": 0, "binary": 1}
+DTYPE = {torch.float32: 0, torch.float64: 1}
+REMAP = {"point": 0, "bijection": 1}
+
+
+class USPGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"uspg error {code}: {msg}")
+        self.code = code
+
+
+class _GridDesc(C.Structure):
+    _fields_ = [("n_rings", C.c_int32), ("n_slices", C.c_int32), ("radius", C.c_double),
+                ("height", C.c_double), ("sector_rule", C.c_int32), ("sector_multiple", C.c_int32),
+                ("sectors", C.POINTER(C.c_int32))]
+
+
+class _ScanDesc(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("n_views", C.c_int32), ("span", C.c_double),
+                ("det_u", C.c_int32), ("det_v", C.c_int32), ("det_half_u", C.c_double),
+                ("det_half_v", C.c_double), ("src_axis", C.c_double), ("src_det", C.c_double),
+                ("weights", C.c_int32), ("coeff_dtype", C.c_int32), ("colour_u", C.c_int32),
+                ("colour_v", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libuspg.so is not built ({LIB_PATH}); run paper_2208_12964_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, D, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    L.uspg_build_grid.argtypes = [C.POINTER(_GridDesc), C.POINTER(P)]
+    L.uspg_grid_info.argtypes = [P, P, P, P, P]
+    L.uspg_grid_tables.argtypes = [P, P, P]
+    L.uspg_free_grid.argtypes = [P]
+    L.uspg_free_grid.restype = None
+    L.uspg_build_coeffs.argtypes = [P, C.POINTER(_ScanDesc), P, C.POINTER(P)]
+    L.uspg_coeffs_info.argtypes = [P, P, P, P, P, P, P]
+    L.uspg_coeffs_row.argtypes = [P, I32, I64, P, P, I32, P]
+    L.uspg_coeffs_conflicts.argtypes = [P, P]
+    L.uspg_free_coeffs.argtypes = [P]
+    L.uspg_free_coeffs.restype = None
+    L.uspg_mart_workspace_bytes.argtypes = [P, I32, D]
+    L.uspg_mart_workspace_bytes.restype = SZ
+    L.mart_run.argtypes = [P, I32, P, P, P, SZ, I32, D, D, P, P]
+    L.uspg_to_cartesian.argtypes = [P, I32, P, P, I32, I32, P]
+    L.uspg_last_error.restype = C.c_char_p
+    for name in ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_build_coeffs",
+                 "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "mart_run",
+                 "uspg_to_cartesian"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise USPGError(rc, lib().uspg_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Grid:
+    """USPG / USCG grid (Sec. II.A): ``uspg_build_grid``."""
+
+    def __init__(self, n_rings: int, n_slices: int = 1, radius: float = 1.0, height: float = 0.0,
+                 sector_rule: str = "multiple", sector_multiple: int = 8, sectors=None):
+        L = lib()
+        self._keep = None
+        ptr = None
+        if sectors is not None:
+            arr = (C.c_int32 * len(sectors))(*[int(x) for x in sectors])
+            self._keep = arr
+            ptr = C.cast(arr, C.POINTER(C.c_int32))
+        d = _GridDesc(n_rings, n_slices, radius, height, SECTORS[sector_rule], sector_multiple, ptr)
+        h = C.c_void_p()
+        _check(L.uspg_build_grid(C.byref(d), C.byref(h)))
+        self.handle = h
+        n_cells, c2d = C.c_int64(), C.c_int64()
+        _check(L.uspg_grid_info(h, C.byref(n_cells), C.byref(c2d), None, None))
+        self.n_cells, self.cells_per_slice = n_cells.value, c2d.value
+        self.n_rings, self.n_slices = n_rings, n_slices
+
+    @classmethod
+    def from_workload(cls, w) -> "Grid":
+        return cls(w.n_rings, w.n_slices, w.radius, w.height, w.sector_rule, w.sector_multiple)
+
+    def tables(self):
+        import numpy as np
+        ng = np.zeros(self.n_rings, dtype=np.int32)
+        head = np.zeros(self.n_rings + 1, dtype=np.int64)
+        _check(lib().uspg_grid_tables(self.handle, ng.ctypes.data_as(C.c_void_p),
+                                      head.ctypes.data_as(C.c_void_p)))
+        return ng, head
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().uspg_free_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Coeffs:
+    """Reference-view coefficients and colouring (Sec. III.A-C):
+    ``uspg_build_coeffs``.  Keeps its grid alive."""
+
+    def __init__(self, grid: Grid, geometry: str, n_views: int, span: float, det_u: int, det_v: int = 1,
+                 det_half_u: float = 1.0, det_half_v: float = 0.0, src_axis: float = 0.0,
+                 src_det: float = 0.0, weights: str = "length", coeff_dtype=torch.float32,
+                 colour=(0, 0), stream=None):
+        L = lib()
+        self.grid = grid
+        d = _ScanDesc(GEOMETRY[geometry], n_views, span, det_u, det_v, det_half_u, det_half_v,
+                      src_axis, src_det, WEIGHTS[weights], DTYPE[coeff_dtype], colour[0], colour[1])
+        h = C.c_void_p()
+        _check(L.uspg_build_coeffs(grid.handle, C.byref(d), C.c_void_p(_stream(stream)), C.byref(h)))
+        self.handle = h
+        self.n_views, self.det_u, self.det_v = n_views, det_u, det_v
+        nnz, nr, ku, kv, mr, db = (C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(),
+                                   C.c_int64())
+        _check(L.uspg_coeffs_info(h, C.byref(nnz), C.byref(nr), C.byref(ku), C.byref(kv), C.byref(mr),
+                                  C.byref(db)))
+        self.nnz, self.n_rays = nnz.value, nr.value
+        self.lattice = (ku.value, kv.value)
+        self.max_row, self.device_bytes = mr.value, db.value
+
+    @classmethod
+    def from_workload(cls, grid: Grid, w, coeff_dtype=torch.float32, colour=(0, 0), stream=None):
+        return cls(grid, w.geometry, w.n_views, w.span, w.det_u, w.det_v, w.det_half_u, w.det_half_v,
+                   w.src_axis, w.src_det, "binary" if w.binary else "length", coeff_dtype, colour, stream)
+
+    def row(self, view: int, ray: int):
+        import numpy as np
+        cap = max(self.max_row, 1)
+        cells = np.zeros(cap, dtype=np.int64)
+        lens = np.zeros(cap)
+        n = C.c_int32()
+        _check(lib().uspg_coeffs_row(self.handle, view, ray, cells.ctypes.data_as(C.c_void_p),
+                                     lens.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
+        return cells[:n.value].copy(), lens[:n.value].copy()
+
+    def conflicts(self):
+        import numpy as np
+        mark = np.zeros(self.n_rays, dtype=np.uint8)
+        _check(lib().uspg_coeffs_conflicts(self.handle, mark.ctypes.data_as(C.c_void_p)))
+        return mark.reshape(self.det_v, self.det_u)
+
+    def workspace_bytes(self, dtype=torch.float32, tol: float = 0.0) -> int:
+        return int(lib().uspg_mart_workspace_bytes(self.handle, DTYPE[dtype], tol))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().uspg_free_coeffs(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dev_check(t: torch.Tensor, name: str):
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous device tensor")
+
+
+def mart(coeffs: Coeffs, proj: torch.Tensor, image: torch.Tensor, n_sweeps: int, beta: float,
+         tol: float = 0.0, work: torch.Tensor | None = None, stream=None) -> int:
+    """Sp-MART in place on ``image`` (paper numbering): ``mart_run``.
+    Returns the number of sweeps run (exact only after a stream sync when tol == 0)."""
+    _dev_check(proj, "proj")
+    _dev_check(image, "image")
+    if proj.dtype != image.dtype or image.dtype not in DTYPE:
+        raise ValueError("proj and image must share dtype float32 or float64")
+    need = coeffs.workspace_bytes(image.dtype, tol)
+    if work is None:
+        work = torch.empty(need, dtype=torch.uint8, device=image.device)
+    _dev_check(work, "work")
+    done = C.c_int32()
+    _check(lib().mart_run(coeffs.handle, DTYPE[image.dtype], C.c_void_p(proj.data_ptr()),
+                          C.c_void_p(image.data_ptr()), C.c_void_p(work.data_ptr()),
+                          work.numel() * work.element_size(), n_sweeps, beta, tol, C.byref(done),
+                          C.c_void_p(_stream(stream))))
+    return done.value
+
+
+def to_cartesian(grid: Grid, image: torch.Tensor, nc: int, mode: str = "point",
+                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """USPG -> Cartesian remap (Sec. II.B): ``uspg_to_cartesian``."""
+    _dev_check(image, "image")
+    if out is None:
+        out = torch.empty((grid.n_slices, nc, nc), dtype=image.dtype, device=image.device)
+    _dev_check(out, "out")
+    _check(lib().uspg_to_cartesian(grid.handle, DTYPE[image.dtype], C.c_void_p(image.data_ptr()),
+                                   C.c_void_p(out.data_ptr()), nc, REMAP[mode], C.c_void_p(_stream(stream))))
+    return out
+
+
+EXPORTED = ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_free_grid",
+            "uspg_build_coeffs", "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts",
+            "uspg_free_coeffs", "uspg_mart_workspace_bytes", "mart_run", "uspg_to_cartesian",
+            "uspg_last_error")
+
+
+def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, colour=(0, 0),
+                sweeps=None, beta=None, remap_nc: int = 0):
+    """Whole path for one workload record: grid, coefficients, MART from a
+    ones image, optional Cartesian remap.  Returns (image, cart, grid, coeffs)."""
+    grid = Grid.from_workload(w)
+    coeffs = Coeffs.from_workload(grid, w, coeff_dtype or dtype, colour)
+    image = torch.ones(grid.n_cells, dtype=dtype, device=proj.device)
+    mart(coeffs, proj.to(dtype).contiguous(), image, w.sweeps if sweeps is None else sweeps,
+         w.beta if beta is None else beta)
+    cart = to_cartesian(grid, image, remap_nc) if remap_nc else None
+    return image, cart, grid, coeffs
+
+
+__all__ = ["Grid", "Coeffs", "mart", "to_cartesian", "reconstruct", "USPGError", "lib", "LIB_PATH",
+           "EXPORTED", "math"]

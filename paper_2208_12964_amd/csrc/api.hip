@@ -1,0 +1,342 @@
+// C ABI entry points: argument checks, handle construction, dispatch.
+#include <cmath>
+#include <cstring>
+
+#include "uspg_internal.hpp"
+
+namespace uspg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg)
+{
+    set_error(msg);
+    return code;
+}
+
+int DevBuf::alloc(size_t n)
+{
+    release();
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, n) != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return fail(USPG_E_NOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    }
+    bytes = n;
+    return USPG_OK;
+}
+
+void DevBuf::release()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+static int current_device(int *dev)
+{
+    USPG_HIP(hipGetDevice(dev));
+    return USPG_OK;
+}
+
+static int check_device(int want)
+{
+    int dev = -1;
+    int rc = current_device(&dev);
+    if (rc != USPG_OK) return rc;
+    if (dev != want) return fail(USPG_E_ARG, "handle belongs to another device than the current one");
+    return USPG_OK;
+}
+
+// Sector counts of the grid rules (Sec. II.A, eq. 1).
+static int sector_table(const uspg_grid_desc *d, std::vector<int32_t> &ng)
+{
+    ng.resize(d->n_rings);
+    for (int i = 0; i < d->n_rings; ++i) {
+        switch (d->sector_rule) {
+        case USPG_SECTORS_PAPER:
+            ng[i] = 4 * (2 * i + 1);
+            break;
+        case USPG_SECTORS_MULTIPLE: {
+            int m = d->sector_multiple;
+            if (m <= 0) return fail(USPG_E_ARG, "sector_multiple must be positive");
+            double need = kTwoPi * (i + 0.5) / m;
+            ng[i] = m * (int)std::ceil(need);
+            break;
+        }
+        case USPG_SECTORS_EXPLICIT:
+            if (!d->sectors) return fail(USPG_E_ARG, "explicit sector rule needs a table");
+            ng[i] = d->sectors[i];
+            break;
+        default:
+            return fail(USPG_E_ARG, "unknown sector rule");
+        }
+        if (ng[i] < 2) return fail(USPG_E_ARG, "every ring needs at least two sectors");
+        // a line dipping two rings below ring i spans at least 2 acos((i-1)/i)
+        // in azimuth; that must exceed one sector so that only the ring just
+        // outside the innermost ring can be entered twice
+        if (i >= 2 && std::acos((double)(i - 1) / i) * ng[i] <= M_PI * (1 + 1e-9))
+            return fail(USPG_E_ARG, "too few sectors in ring " + std::to_string(i));
+    }
+    return USPG_OK;
+}
+
+}  // namespace uspg
+
+using namespace uspg;
+
+extern "C" {
+
+const char *uspg_last_error(void) { return g_last_error.c_str(); }
+
+int uspg_build_grid(const uspg_grid_desc *desc, uspg_grid **out)
+{
+    if (!desc || !out) return fail(USPG_E_ARG, "null argument");
+    *out = nullptr;
+    if (desc->n_rings <= 0 || desc->n_slices <= 0 || !(desc->radius > 0))
+        return fail(USPG_E_ARG, "n_rings, n_slices and radius must be positive");
+    if (desc->n_slices > 1 && !(desc->height > 0)) return fail(USPG_E_ARG, "height must be positive");
+    auto *g = new uspg_grid();
+    int rc = sector_table(desc, g->ng);
+    if (rc != USPG_OK) { delete g; return rc; }
+    g->nr = desc->n_rings;
+    g->nz = desc->n_slices;
+    g->R = desc->radius;
+    g->H = desc->n_slices > 1 ? desc->height : (desc->height > 0 ? desc->height : 0.0);
+    g->r = g->R / g->nr;
+    g->h = g->nz > 1 || g->H > 0 ? g->H / g->nz : 0.0;
+    g->z0 = -g->H / 2;
+    g->rule = desc->sector_rule;
+    g->head.assign(g->nr + 1, 0);
+    for (int i = 0; i < g->nr; ++i) g->head[i + 1] = g->head[i] + g->ng[i];   // eq. 2
+    g->c2d = g->head[g->nr];
+    g->ncells = g->c2d * g->nz;
+    if (g->ncells >= (int64_t)1 << 31) { delete g; return fail(USPG_E_ARG, "more than 2^31 cells"); }
+    if ((rc = current_device(&g->device)) != USPG_OK) { delete g; return rc; }
+    std::vector<double2> cs(g->c2d);
+    for (int i = 0; i < g->nr; ++i)
+        for (int b = 0; b < g->ng[i]; ++b) {
+            double ang = b * (kTwoPi / g->ng[i]);
+            cs[g->head[i] + b] = make_double2(std::cos(ang), std::sin(ang));
+        }
+    if ((rc = g->d_ng.alloc(sizeof(int32_t) * g->nr)) != USPG_OK ||
+        (rc = g->d_head.alloc(sizeof(int64_t) * (g->nr + 1))) != USPG_OK ||
+        (rc = g->d_cs.alloc(sizeof(double2) * g->c2d)) != USPG_OK) {
+        uspg_free_grid(g);
+        return rc;
+    }
+    if (hipMemcpy(g->d_ng.p, g->ng.data(), sizeof(int32_t) * g->nr, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->d_head.p, g->head.data(), sizeof(int64_t) * (g->nr + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->d_cs.p, cs.data(), sizeof(double2) * g->c2d, hipMemcpyHostToDevice) != hipSuccess) {
+        uspg_free_grid(g);
+        return fail(USPG_E_HIP, "uploading grid tables failed");
+    }
+    *out = g;
+    return USPG_OK;
+}
+
+int uspg_grid_info(const uspg_grid *g, int64_t *n_cells, int64_t *cells_per_slice, int32_t *n_rings,
+                   int32_t *n_slices)
+{
+    if (!g) return fail(USPG_E_ARG, "null grid");
+    if (n_cells) *n_cells = g->ncells;
+    if (cells_per_slice) *cells_per_slice = g->c2d;
+    if (n_rings) *n_rings = g->nr;
+    if (n_slices) *n_slices = g->nz;
+    return USPG_OK;
+}
+
+int uspg_grid_tables(const uspg_grid *g, int32_t *sectors, int64_t *heads)
+{
+    if (!g) return fail(USPG_E_ARG, "null grid");
+    if (sectors) std::memcpy(sectors, g->ng.data(), sizeof(int32_t) * g->nr);
+    if (heads) std::memcpy(heads, g->head.data(), sizeof(int64_t) * (g->nr + 1));
+    return USPG_OK;
+}
+
+void uspg_free_grid(uspg_grid *g)
+{
+    if (!g) return;
+    g->d_ng.release();
+    g->d_head.release();
+    g->d_cs.release();
+    delete g;
+}
+
+int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *sc, void *stream, uspg_coeffs **out)
+{
+    if (!g || !sc || !out) return fail(USPG_E_ARG, "null argument");
+    *out = nullptr;
+    int rc = check_device(g->device);
+    if (rc != USPG_OK) return rc;
+    const bool cone = sc->geometry == USPG_CONE_3D;
+    if (sc->geometry < USPG_PARALLEL_2D || sc->geometry > USPG_CONE_3D) return fail(USPG_E_ARG, "unknown geometry");
+    if (sc->n_views <= 0 || !(sc->span > 0) || sc->det_u <= 0 || sc->det_v <= 0 || !(sc->det_half_u > 0))
+        return fail(USPG_E_ARG, "views, span, detector size and width must be positive");
+    if (!cone && (g->nz != 1 || sc->det_v != 1)) return fail(USPG_E_ARG, "2D scans need a 2D grid and det_v == 1");
+    if (cone && !(g->H > 0 && sc->det_half_v > 0)) return fail(USPG_E_ARG, "cone beam needs a cylinder and det_half_v > 0");
+    if (sc->geometry != USPG_PARALLEL_2D && !(sc->src_axis > g->R && sc->src_det > 0))
+        return fail(USPG_E_ARG, "the source must lie outside the cylinder");
+    if (sc->weights != USPG_WEIGHTS_LENGTH && sc->weights != USPG_WEIGHTS_BINARY) return fail(USPG_E_ARG, "weights");
+    if (sc->coeff_dtype != USPG_F32 && sc->coeff_dtype != USPG_F64) return fail(USPG_E_ARG, "coeff_dtype");
+    if ((int64_t)sc->det_u * sc->det_v >= (int64_t)1 << 31) return fail(USPG_E_ARG, "too many rays");
+    // view group: a view step must be a whole number of sectors in every ring
+    double qf = sc->n_views * kTwoPi / sc->span;
+    int q = (int)std::floor(qf + 0.5);
+    if (q <= 0 || std::fabs(qf - q) > 1e-9) return fail(USPG_E_SHIFT, "n_views * 2 pi / span is not an integer");
+    for (int i = 0; i < g->nr; ++i)
+        if (g->ng[i] % q)
+            return fail(USPG_E_SHIFT, "ring " + std::to_string(i) + " has " + std::to_string(g->ng[i]) +
+                                          " sectors, not a multiple of " + std::to_string(q));
+    auto *c = new uspg_coeffs();
+    c->g = g;
+    c->scan = *sc;
+    c->device = g->device;
+    c->q = q;
+    c->kq.resize(g->nr);
+    c->hq.resize(g->nr + 1);
+    c->hq[0] = 0;
+    for (int i = 0; i < g->nr; ++i) {
+        c->kq[i] = g->ng[i] / q;
+        c->hq[i + 1] = c->hq[i] + c->kq[i];
+    }
+    c->Cq = c->hq[g->nr];
+    c->Wc = (int64_t)g->nz * c->Cq;
+    c->Wtot = q * c->Wc;
+    c->nrays = (int64_t)sc->det_u * sc->det_v;
+    std::vector<int32_t> ring_of(c->Cq);
+    for (int i = 0; i < g->nr; ++i)
+        for (int b = 0; b < c->kq[i]; ++b) ring_of[c->hq[i] + b] = i;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = c->d_kq.alloc(sizeof(int32_t) * g->nr)) != USPG_OK ||
+        (rc = c->d_hq.alloc(sizeof(int32_t) * (g->nr + 1))) != USPG_OK ||
+        (rc = c->d_ring_of_off.alloc(sizeof(int32_t) * c->Cq)) != USPG_OK) {
+        uspg_free_coeffs(c);
+        return rc;
+    }
+    if (hipMemcpy(c->d_kq.p, c->kq.data(), sizeof(int32_t) * g->nr, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_hq.p, c->hq.data(), sizeof(int32_t) * (g->nr + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_ring_of_off.p, ring_of.data(), sizeof(int32_t) * c->Cq, hipMemcpyHostToDevice) != hipSuccess) {
+        uspg_free_coeffs(c);
+        return fail(USPG_E_HIP, "uploading wedge tables failed");
+    }
+    if ((rc = trace_reference_view(c, s)) != USPG_OK || (rc = colour_reference_view(c, s)) != USPG_OK) {
+        uspg_free_coeffs(c);
+        return rc;
+    }
+    c->device_bytes = (int64_t)(c->rowptr.bytes + c->ids.bytes + c->a.bytes + c->d_kq.bytes +
+                                c->d_hq.bytes + c->d_ring_of_off.bytes);
+    *out = c;
+    return USPG_OK;
+}
+
+int uspg_coeffs_info(const uspg_coeffs *c, int64_t *nnz_ref, int64_t *n_rays, int32_t *colour_u,
+                     int32_t *colour_v, int32_t *max_row, int64_t *device_bytes)
+{
+    if (!c) return fail(USPG_E_ARG, "null coefficients");
+    if (nnz_ref) *nnz_ref = c->nnz;
+    if (n_rays) *n_rays = c->nrays;
+    if (colour_u) *colour_u = c->Ku;
+    if (colour_v) *colour_v = c->Kv;
+    if (max_row) *max_row = c->max_row;
+    if (device_bytes) *device_bytes = c->device_bytes;
+    return USPG_OK;
+}
+
+int uspg_coeffs_row(const uspg_coeffs *c, int32_t view, int64_t ray, int64_t *cells, double *lengths,
+                    int32_t cap, int32_t *n)
+{
+    if (!c || !n) return fail(USPG_E_ARG, "null argument");
+    if (view < 0 || view >= c->scan.n_views || ray < 0 || ray >= c->nrays) return fail(USPG_E_ARG, "view or ray out of range");
+    int rc = check_device(c->device);
+    if (rc != USPG_OK) return rc;
+    int64_t rp[2];
+    USPG_HIP(hipMemcpy(rp, c->rowptr.as<int64_t>() + ray, sizeof(rp), hipMemcpyDeviceToHost));
+    int32_t len = (int32_t)(rp[1] - rp[0]);
+    *n = len;
+    if (len > cap) return fail(USPG_E_NOMEM, "row longer than cap");
+    if (len == 0) return USPG_OK;
+    if (!cells || !lengths) return fail(USPG_E_ARG, "null output");
+    std::vector<uint32_t> ids(len);
+    USPG_HIP(hipMemcpy(ids.data(), c->ids.as<uint32_t>() + rp[0], sizeof(uint32_t) * len, hipMemcpyDeviceToHost));
+    if (c->scan.coeff_dtype == USPG_F64) {
+        USPG_HIP(hipMemcpy(lengths, c->a.as<double>() + rp[0], sizeof(double) * len, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> a(len);
+        USPG_HIP(hipMemcpy(a.data(), c->a.as<float>() + rp[0], sizeof(float) * len, hipMemcpyDeviceToHost));
+        for (int j = 0; j < len; ++j) lengths[j] = a[j];
+    }
+    const uspg_grid *g = c->g;
+    for (int j = 0; j < len; ++j) {
+        int64_t x = ((int64_t)ids[j] + (int64_t)view * c->Wc) % c->Wtot;
+        int64_t aw = x / c->Wc, rem = x % c->Wc, k = rem / c->Cq, o = rem % c->Cq;
+        int i = 0;
+        while (i + 1 < g->nr && c->hq[i + 1] <= o) ++i;
+        int64_t s = aw * c->kq[i] + (o - c->hq[i]);
+        cells[j] = k * g->c2d + g->head[i] + s;
+    }
+    return USPG_OK;
+}
+
+int uspg_coeffs_conflicts(const uspg_coeffs *c, uint8_t *mark)
+{
+    if (!c || !mark) return fail(USPG_E_ARG, "null argument");
+    std::memcpy(mark, c->mark.data(), c->mark.size());
+    return USPG_OK;
+}
+
+void uspg_free_coeffs(uspg_coeffs *c)
+{
+    if (!c) return;
+    c->rowptr.release();
+    c->ids.release();
+    c->a.release();
+    c->d_kq.release();
+    c->d_hq.release();
+    c->d_ring_of_off.release();
+    delete c;
+}
+
+size_t uspg_mart_workspace_bytes(const uspg_coeffs *c, int32_t dtype, double tol)
+{
+    if (!c) return 0;
+    size_t sz = dtype == USPG_F64 ? sizeof(double) : sizeof(float);
+    size_t n = (size_t)c->g->ncells * sz;
+    return tol > 0 ? 2 * n + 16 : n;
+}
+
+int mart_run(const uspg_coeffs *c, int32_t dtype, const void *proj, void *image, void *work,
+             size_t work_bytes, int32_t n_sweeps, double beta, double tol, int32_t *sweeps_done,
+             void *stream)
+{
+    if (!c || !proj || !image || !work) return fail(USPG_E_ARG, "null argument");
+    if (dtype != USPG_F32 && dtype != USPG_F64) return fail(USPG_E_ARG, "dtype");
+    if (n_sweeps < 0 || !(beta > 0) || !(tol >= 0)) return fail(USPG_E_ARG, "n_sweeps >= 0, beta > 0, tol >= 0");
+    if (work_bytes < uspg_mart_workspace_bytes(c, dtype, tol)) return fail(USPG_E_NOMEM, "work space too small");
+    int rc = check_device(c->device);
+    if (rc != USPG_OK) return rc;
+    return mart_launch(c, dtype, proj, image, work, n_sweeps, beta, tol, sweeps_done, (hipStream_t)stream);
+}
+
+int uspg_to_cartesian(const uspg_grid *g, int32_t dtype, const void *image, void *cart, int32_t nc,
+                      int32_t mode, void *stream)
+{
+    if (!g || !image || !cart) return fail(USPG_E_ARG, "null argument");
+    if (dtype != USPG_F32 && dtype != USPG_F64) return fail(USPG_E_ARG, "dtype");
+    if (nc <= 0 || (int64_t)nc * nc >= (int64_t)1 << 31) return fail(USPG_E_ARG, "nc out of range");
+    if (mode == USPG_REMAP_BIJECTION) {
+        if (nc != 2 * g->nr) return fail(USPG_E_ARG, "bijection needs nc == 2 n_rings");
+        for (int i = 0; i < g->nr; ++i)
+            if (g->ng[i] != 4 * (2 * i + 1)) return fail(USPG_E_ARG, "bijection needs the paper's sector rule");
+    } else if (mode != USPG_REMAP_POINT) {
+        return fail(USPG_E_ARG, "unknown remap mode");
+    }
+    int rc = check_device(g->device);
+    if (rc != USPG_OK) return rc;
+    return remap_launch(g, dtype, image, cart, nc, mode, (hipStream_t)stream);
+}
+
+}  // extern "C"

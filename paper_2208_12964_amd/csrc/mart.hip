@@ -1,0 +1,316 @@
+// Sp-MART on the device (Sec. III.D, eqs. 17-19).
+//
+// The image lives in the wedge-major layout during the solve, so the rows of
+// view v are the reference rows with every cell id shifted by v * Wc modulo
+// the image size (one add and one conditional subtract per coefficient).
+// One batch = one (view, colour class): all rays of the class are cell
+// disjoint, so each wavefront takes one ray and updates its cells without
+// atomics, exactly as if the rays were applied one after another.
+//
+// Per ray (wavefront of 64 lanes, lane j handles coefficients j, j+64, ...):
+//   load ids / coefficients (coalesced), rotate ids, gather f,
+//   Pbar = sum a f and a_max by wavefront reductions (fixed order),
+//   c = beta (P / Pbar - 1) / a_max,  f_j <- f_j (1 + c a_j)   (eq. 18).
+// Rows up to 64 * NCH coefficients stay in registers between the gather and
+// the scatter; longer rows are re-read in a second pass.
+#include "uspg_internal.hpp"
+
+namespace uspg {
+namespace {
+
+constexpr int kWaves = 4;             // wavefronts per workgroup
+constexpr int kBlock = 64 * kWaves;
+
+template <class T>
+__device__ inline T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <class T>
+__device__ inline T wave_max(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        T o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+template <class T, class TC>
+struct BatchArgs {
+    const int64_t *rowptr;
+    const uint32_t *ids;
+    const TC *a;
+    const T *P;        // projections of the view, [rays]
+    T *f;              // wedge-major image
+    uint32_t shift;    // v * Wc (mod Wtot)
+    uint32_t wtot;
+    int U, cu, cw, Ku, Kv, nu, ncls, nblk;
+    T beta;
+};
+
+// Workgroups are dispatched round robin over the 8 XCDs; renumber them so
+// that each XCD owns one contiguous run of the class's rays (neighbouring rays
+// touch neighbouring cells, which then share that XCD's L2).
+__device__ inline int xcd_block(int b, int nb)
+{
+    int xcd = b & 7, idx = b >> 3;
+    int per = nb >> 3, rem = nb & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+template <class T, class TC, int NCH>
+__global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
+{
+    const int lane = threadIdx.x & 63;
+    const int x = xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6);
+    if (x >= A.ncls) return;
+    const int w = A.cw + (x / A.nu) * A.Kv;
+    const int u = A.cu + (x % A.nu) * A.Ku;
+    const int64_t r = (int64_t)w * A.U + u;
+    const int64_t beg = A.rowptr[r];
+    const int n = (int)(A.rowptr[r + 1] - beg);
+    if (n == 0) return;
+    const uint32_t *ids = A.ids + beg;
+    const TC *a = A.a + beg;
+
+    if (NCH > 0 && n <= 64 * NCH) {
+        uint32_t id[NCH > 0 ? NCH : 1];
+        T av[NCH > 0 ? NCH : 1], fv[NCH > 0 ? NCH : 1];
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int j = lane + 64 * k;
+            id[k] = 0;
+            av[k] = T(0);
+            if (j < n) {
+                uint32_t t = ids[j] + A.shift;
+                id[k] = t >= A.wtot ? t - A.wtot : t;
+                av[k] = (T)a[j];
+            }
+        }
+        T acc = T(0), amax = T(0);
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int j = lane + 64 * k;
+            fv[k] = T(0);
+            if (j < n) {
+                fv[k] = A.f[id[k]];
+                acc += av[k] * fv[k];
+                amax = av[k] > amax ? av[k] : amax;
+            }
+        }
+        acc = wave_sum(acc);
+        amax = wave_max(amax);
+        if (!(acc > T(0)) || !(amax > T(0))) return;
+        const T c = A.beta * (A.P[r] / acc - T(1)) / amax;
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int j = lane + 64 * k;
+            if (j < n) A.f[id[k]] = fv[k] * (T(1) + c * av[k]);
+        }
+        return;
+    }
+    // long rows: forward pass, then re-read and update
+    T acc = T(0), amax = T(0);
+    for (int j = lane; j < n; j += 64) {
+        uint32_t t = ids[j] + A.shift;
+        t = t >= A.wtot ? t - A.wtot : t;
+        T av = (T)a[j];
+        acc += av * A.f[t];
+        amax = av > amax ? av : amax;
+    }
+    acc = wave_sum(acc);
+    amax = wave_max(amax);
+    if (!(acc > T(0)) || !(amax > T(0))) return;
+    const T c = A.beta * (A.P[r] / acc - T(1)) / amax;
+    for (int j = lane; j < n; j += 64) {
+        uint32_t t = ids[j] + A.shift;
+        t = t >= A.wtot ? t - A.wtot : t;
+        A.f[t] = A.f[t] * (T(1) + c * (T)a[j]);
+    }
+}
+
+// Layout maps between the paper's numbering and the wedge-major layout.
+struct LayoutArgs {
+    const int32_t *ring_of_off, *kq, *hq;
+    const int64_t *head;
+    uint32_t Cq, Wc, c2d, ncells;
+};
+
+__device__ inline uint32_t native_to_paper(uint32_t x, const LayoutArgs &L)
+{
+    uint32_t aw = x / L.Wc;
+    uint32_t rem = x - aw * L.Wc;
+    uint32_t k = rem / L.Cq;
+    uint32_t o = rem - k * L.Cq;
+    int i = L.ring_of_off[o];
+    uint32_t b = o - (uint32_t)L.hq[i];
+    uint32_t s = aw * (uint32_t)L.kq[i] + b;
+    return k * L.c2d + (uint32_t)L.head[i] + s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void to_native(LayoutArgs L, const T *paper, T *native)
+{
+    uint32_t x = blockIdx.x * 256u + threadIdx.x;
+    if (x < L.ncells) native[x] = paper[native_to_paper(x, L)];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void to_paper(LayoutArgs L, const T *native, T *paper)
+{
+    uint32_t x = blockIdx.x * 256u + threadIdx.x;
+    if (x < L.ncells) paper[native_to_paper(x, L)] = native[x];
+}
+
+// max_j |f_j - g_j| / g_j (eq. 19), values are positive so their bit
+// patterns order like unsigned integers.
+template <class T> struct Bits;
+template <> struct Bits<float> { using U = unsigned int; };
+template <> struct Bits<double> { using U = unsigned long long; };
+
+template <class T>
+__global__ __launch_bounds__(256) void max_rel_change(const T *f, const T *g, uint32_t n,
+                                                      typename Bits<T>::U *out)
+{
+    __shared__ T sh[256];
+    T m = T(0);
+    for (uint32_t x = blockIdx.x * 256u + threadIdx.x; x < n; x += gridDim.x * 256u) {
+        T d = (f[x] - g[x]) / g[x];
+        d = d < T(0) ? -d : d;
+        m = d > m ? d : m;
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x + s] > sh[threadIdx.x] ? sh[threadIdx.x + s] : sh[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        T v = sh[0];
+        typename Bits<T>::U bits;
+        __builtin_memcpy(&bits, &v, sizeof(v));
+        atomicMax(out, bits);
+    }
+}
+
+template <class T, class TC, int NCH>
+void launch_batch(const BatchArgs<T, TC> &A, hipStream_t s)
+{
+    hipLaunchKernelGGL((mart_batch<T, TC, NCH>), dim3(A.nblk), dim3(kBlock), 0, s, A);
+}
+
+template <class T, class TC>
+void launch_batch_n(int nch, const BatchArgs<T, TC> &A, hipStream_t s)
+{
+    switch (nch) {
+    case 1: launch_batch<T, TC, 1>(A, s); break;
+    case 2: launch_batch<T, TC, 2>(A, s); break;
+    case 4: launch_batch<T, TC, 4>(A, s); break;
+    case 8: launch_batch<T, TC, 8>(A, s); break;
+    case 12: launch_batch<T, TC, 12>(A, s); break;
+    case 16: launch_batch<T, TC, 16>(A, s); break;
+    default: launch_batch<T, TC, 0>(A, s); break;
+    }
+}
+
+int pick_nch(int max_row)
+{
+    if (max_row <= 64) return 1;
+    if (max_row <= 128) return 2;
+    if (max_row <= 256) return 4;
+    if (max_row <= 512) return 8;
+    if (max_row <= 768) return 12;
+    if (max_row <= 1024) return 16;
+    return 0;
+}
+
+template <class T, class TC>
+int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_sweeps, double beta,
+              double tol, int32_t *sweeps_done, hipStream_t s)
+{
+    const uspg_grid *g = c->g;
+    const uint32_t ncells = (uint32_t)g->ncells;
+    T *nat = static_cast<T *>(work);
+    T *old = tol > 0 ? nat + ncells : nullptr;
+    using UB = typename Bits<T>::U;
+    UB *mx = tol > 0 ? reinterpret_cast<UB *>(old + ncells) : nullptr;
+
+    LayoutArgs L;
+    L.ring_of_off = c->d_ring_of_off.as<int32_t>();
+    L.kq = c->d_kq.as<int32_t>();
+    L.hq = c->d_hq.as<int32_t>();
+    L.head = g->d_head.as<int64_t>();
+    L.Cq = (uint32_t)c->Cq; L.Wc = (uint32_t)c->Wc; L.c2d = (uint32_t)g->c2d; L.ncells = ncells;
+    const unsigned pb = (ncells + 255) / 256;
+    hipLaunchKernelGGL(to_native<T>, dim3(pb), dim3(256), 0, s, L, image, nat);
+
+    BatchArgs<T, TC> A{};
+    A.rowptr = c->rowptr.as<int64_t>();
+    A.ids = c->ids.as<uint32_t>();
+    A.a = c->a.as<TC>();
+    A.f = nat;
+    A.wtot = (uint32_t)c->Wtot;
+    A.U = c->scan.det_u;
+    A.Ku = c->Ku; A.Kv = c->Kv;
+    A.beta = (T)beta;
+    const int nch = pick_nch(c->max_row);
+    const int K = c->Ku * c->Kv;
+    int done = 0;
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        if (tol > 0) USPG_HIP(hipMemcpyAsync(old, nat, sizeof(T) * ncells, hipMemcpyDeviceToDevice, s));
+        for (int v = 0; v < c->scan.n_views; ++v) {
+            A.P = proj + (int64_t)v * c->nrays;
+            A.shift = (uint32_t)(((int64_t)v * c->Wc) % c->Wtot);
+            for (int cl = 0; cl < K; ++cl) {
+                A.cu = cl % c->Ku;
+                A.cw = cl / c->Ku;
+                A.nu = (c->scan.det_u - A.cu + c->Ku - 1) / c->Ku;
+                const int nw = (c->scan.det_v - A.cw + c->Kv - 1) / c->Kv;
+                A.ncls = A.nu * nw;
+                A.nblk = (A.ncls + kWaves - 1) / kWaves;
+                if (A.ncls == 0) continue;
+                launch_batch_n<T, TC>(nch, A, s);
+            }
+        }
+        USPG_HIP(hipGetLastError());
+        ++done;
+        if (tol > 0) {
+            USPG_HIP(hipMemsetAsync(mx, 0, sizeof(UB), s));
+            unsigned nb = pb < 4096 ? pb : 4096;
+            hipLaunchKernelGGL(max_rel_change<T>, dim3(nb), dim3(256), 0, s, nat, old, ncells, mx);
+            UB hb = 0;
+            USPG_HIP(hipMemcpyAsync(&hb, mx, sizeof(UB), hipMemcpyDeviceToHost, s));
+            USPG_HIP(hipStreamSynchronize(s));
+            T hv;
+            __builtin_memcpy(&hv, &hb, sizeof(hv));
+            if ((double)hv <= tol) break;
+        }
+    }
+    hipLaunchKernelGGL(to_paper<T>, dim3(pb), dim3(256), 0, s, L, nat, image);
+    USPG_HIP(hipGetLastError());
+    if (sweeps_done) *sweeps_done = done;
+    return USPG_OK;
+}
+
+}  // namespace
+
+int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work,
+                int n_sweeps, double beta, double tol, int32_t *sweeps_done, hipStream_t s)
+{
+    const bool cf64 = c->scan.coeff_dtype == USPG_F64;
+    if (dtype == USPG_F32) {
+        if (cf64)
+            return run_typed<float, double>(c, (const float *)proj, (float *)image, work, n_sweeps, beta, tol, sweeps_done, s);
+        return run_typed<float, float>(c, (const float *)proj, (float *)image, work, n_sweeps, beta, tol, sweeps_done, s);
+    }
+    if (cf64)
+        return run_typed<double, double>(c, (const double *)proj, (double *)image, work, n_sweeps, beta, tol, sweeps_done, s);
+    return run_typed<double, float>(c, (const double *)proj, (double *)image, work, n_sweeps, beta, tol, sweeps_done, s);
+}
+
+}  // namespace uspg

@@ -1,0 +1,94 @@
+// Internal declarations of the USPG / USCG MART library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/uspg.h"
+
+namespace uspg {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Thread-local error message behind uspg_last_error().
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define USPG_HIP(expr)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::uspg::fail(USPG_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Device buffer owned by a handle.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    int alloc(size_t n);
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+}  // namespace uspg
+
+// Grid handle: host tables plus their device copies.
+struct uspg_grid {
+    int nr = 0, nz = 0;
+    double R = 0, H = 0, r = 0, h = 0, z0 = 0;
+    int rule = 0;
+    std::vector<int32_t> ng;     // sectors per ring
+    std::vector<int64_t> head;   // ring heads, nr + 1 entries
+    int64_t c2d = 0, ncells = 0;
+    int device = 0;
+    uspg::DevBuf d_ng, d_head;   // int32 [nr], int64 [nr + 1]
+    uspg::DevBuf d_cs;           // double2 [c2d]: cos / sin of every sector's lower boundary
+};
+
+// Coefficient handle: reference-view rows in the device (wedge-major) cell
+// numbering, lattice colouring and the tables of the wedge layout.
+//
+// Wedge-major layout: with q view steps per turn and k_i = n_g(i) / q sectors
+// of ring i per wedge, sector s = a k_i + b of ring i in slice k is stored at
+//     a * Wc + k * Cq + hq_i + b,   Cq = sum_i k_i,  Wc = Nz * Cq,
+// so rotating by v view steps adds v * Wc modulo q * Wc.
+struct uspg_coeffs {
+    const uspg_grid *g = nullptr;
+    uspg_scan_desc scan{};
+    int device = 0;
+    int q = 0;
+    std::vector<int32_t> kq, hq;  // per ring
+    int64_t Cq = 0, Wc = 0, Wtot = 0;
+    int64_t nrays = 0, nnz = 0;
+    int32_t max_row = 0;
+    int Ku = 1, Kv = 1;
+    std::vector<uint8_t> mark;    // conflict offsets [det_v][det_u]
+    uspg::DevBuf rowptr;          // int64 [nrays + 1]
+    uspg::DevBuf ids;             // uint32 [nnz]
+    uspg::DevBuf a;               // float or double [nnz]
+    uspg::DevBuf d_kq, d_hq;      // int32 [nr]
+    uspg::DevBuf d_ring_of_off;   // int32 [Cq]: ring of each within-wedge offset
+    int64_t device_bytes = 0;
+};
+
+namespace uspg {
+
+
+// trace.hip
+int trace_reference_view(uspg_coeffs *c, hipStream_t s);
+// colour.hip
+int colour_reference_view(uspg_coeffs *c, hipStream_t s);
+// scan.hip
+int exclusive_scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, hipStream_t s);
+int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s);
+// mart.hip
+int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work,
+                int n_sweeps, double beta, double tol, int32_t *sweeps_done, hipStream_t s);
+// remap.hip
+int remap_launch(const uspg_grid *g, int dtype, const void *image, void *cart, int nc, int mode,
+                 hipStream_t s);
+
+}  // namespace uspg

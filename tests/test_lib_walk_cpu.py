@@ -1,0 +1,170 @@
+"""The library's reference-ray walk (host build of trace_walk.hpp) against the
+oracle's direct trace, on the CPU: same cells, lengths equal up to rounding,
+and the wedge-major index shift reproduces every view's rows."""
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+BUILD = os.path.join(HERE, "_build")
+LEN_RTOL, LEN_ATOL = 1e-9, 1e-10
+GEOM = {"parallel2d": 0, "fan2d": 1, "cone3d": 2}
+
+
+@pytest.fixture(scope="module")
+def hw():
+    os.makedirs(BUILD, exist_ok=True)
+    so = os.path.join(BUILD, "host_walk.so")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", os.path.join(HERE, "host_walk.cpp"),
+                    "-o", so], check=True)
+    L = C.CDLL(so)
+    L.hw_setup.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_int, C.c_int,
+                           C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
+    L.hw_trace.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int]
+    return L
+
+
+class Walk:
+    def __init__(self, L, w, o):
+        self.L, self.w, self.o = L, w, o
+        q = round(w.n_views * 2 * math.pi / w.span)
+        self.q = q
+        ng = np.ascontiguousarray(o.ng, dtype=np.int32)
+        rc = L.hw_setup(w.n_rings, w.n_slices, w.radius, w.height, ng.ctypes.data, q, GEOM[w.geometry],
+                        int(w.is3d), w.det_u, w.det_v, w.det_half_u, w.det_half_v, w.src_axis, w.src_det)
+        assert rc == 0
+        self.kq = o.ng // q
+        self.hq = np.concatenate([[0], np.cumsum(self.kq)])
+        self.Cq = int(self.hq[-1])
+        self.Wc = w.n_slices * self.Cq
+        self.cap = 8 * (w.n_rings + w.n_slices) + 64
+
+    def row(self, r):
+        ids = np.zeros(self.cap, dtype=np.uint32)
+        lens = np.zeros(self.cap)
+        n = self.L.hw_trace(r, ids.ctypes.data, lens.ctypes.data, self.cap)
+        assert n >= 0
+        return ids[:n].astype(np.int64), lens[:n]
+
+    def to_paper(self, x, view=0):
+        x = (x + view * self.Wc) % (self.q * self.Wc)
+        a, rem = x // self.Wc, x % self.Wc
+        k, off = rem // self.Cq, rem % self.Cq
+        i = np.searchsorted(self.hq, off, side="right") - 1
+        s = a * self.kq[i] + (off - self.hq[i])
+        return k * self.o.head[-1] + self.o.head[i] + s
+
+
+def compare(c1, l1, c2, l2):
+    assert len(c1) == len(set(c1.tolist()))
+    ia, ib = np.argsort(c1), np.argsort(c2)
+    assert np.array_equal(c1[ia], c2[ib])
+    assert np.allclose(l1[ia], l2[ib], rtol=LEN_RTOL, atol=LEN_ATOL)
+
+
+def on_axis(o, r):
+    """A view-0 ray through the axis lies on the x axis, which is a sector
+    boundary of every ring: either side is a correct cell (ties)."""
+    S, D = o.ray(0, r)
+    e = D - S
+    return abs(S[0] * e[1] - S[1] * e[0]) < 1e-12
+
+
+def compare_by_ring(wk, o, cells, lens, c2, l2):
+    """Tie rays: lengths per (slice, ring) must agree."""
+    def key(x):
+        c2d = o.head[-1]
+        rem = x % c2d
+        return (x // c2d) * 100000 + np.searchsorted(o.head, rem, side="right") - 1
+    k1, k2 = key(cells), key(c2)
+    for k in set(k1.tolist()) | set(k2.tolist()):
+        assert abs(lens[k1 == k].sum() - l2[k2 == k].sum()) < 1e-9
+
+
+def cases():
+    return {
+        "par2d": synth.get("par2d-32r-8v"),
+        "par2d-paper-rule": synth.Workload(name="pp", geometry="parallel2d", n_rings=16,
+                                           sector_rule="paper", n_views=2, span=math.pi, det_u=33),
+        "fan2d-odd": synth.Workload(name="fan", geometry="fan2d", n_rings=20, sector_multiple=10,
+                                    n_views=10, span=2 * math.pi, det_u=41, det_half_u=2.2,
+                                    src_axis=4.0, src_det=8.0),
+        "cone-small": synth.small_cone(n_rings=16, n_views=8, det=32, m=8),
+        "cone-odd": synth.small_cone(n_rings=10, n_views=4, det=15, m=4, n_slices=7),
+    }
+
+
+@pytest.mark.parametrize("name", list(cases()))
+def test_walk_equals_oracle_all_views(hw, name):
+    w = cases()[name]
+    o = Oracle(w)
+    wk = Walk(hw, w, o)
+    rows = [wk.row(r) for r in range(o.n_rays)]
+    for v in range(w.n_views):
+        direct = o.trace_view(v)
+        for r in range(o.n_rays):
+            ids, lens = rows[r]
+            c2, l2 = direct.row(r)
+            if on_axis(o, r):
+                compare_by_ring(wk, o, wk.to_paper(ids, v), lens, c2, l2)
+                continue
+            compare(wk.to_paper(ids, v), lens, c2, l2)
+
+
+@pytest.mark.parametrize("name,step", [("cone-128r-16v", 331), ("cone-256r-32v-hc", 2609)])
+def test_walk_equals_oracle_sampled_full_size(hw, name, step):
+    w = synth.get(name)
+    o = Oracle(w)
+    wk = Walk(hw, w, o)
+    rng = np.random.default_rng(1)
+    rays = list(range(0, o.n_rays, step)) + list(rng.integers(0, o.n_rays, 40))
+    for r in rays:
+        ids, lens = wk.row(int(r))
+        for v in (0, w.n_views - 1):
+            S, D = o.ray(v, int(r))
+            c2, l2 = o.trace_line(S, D)
+            compare(wk.to_paper(ids, v), lens, c2, l2)
+
+
+def test_walk_random_and_near_tangent_lines(hw):
+    # arbitrary lines, including ones that dip just below a circle in the middle
+    # of a sector of the ring outside it (that sector is entered twice and the
+    # two visits must be merged into one entry)
+    from test_oracle_trace import _near_tangent_rays, cell_of_points
+    hw.hw_trace_line.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+    for w in (synth.Workload(name="pp", geometry="parallel2d", n_rings=5, sector_rule="paper",
+                             n_views=1, span=2 * math.pi, det_u=8),
+              synth.small_cone(n_rings=6, n_views=8, det=8, m=8, n_slices=5)):
+        o = Oracle(w)
+        wk = Walk(hw, w, o)
+        rng = np.random.default_rng(3)
+        lines = _near_tangent_rays(o, rng, 300)
+        for _ in range(300):
+            lines.append((np.array([*rng.uniform(-3, 3, 2), rng.uniform(-0.9, 0.9) if w.is3d else 0]),
+                          np.array([*rng.uniform(-3, 3, 2), rng.uniform(-0.9, 0.9) if w.is3d else 0])))
+        reentries = 0
+        for S, D in lines:
+            S = np.ascontiguousarray(S, dtype=np.float64)
+            D = np.ascontiguousarray(D, dtype=np.float64)
+            ids = np.zeros(wk.cap, dtype=np.uint32)
+            lens = np.zeros(wk.cap)
+            n = hw.hw_trace_line(S.ctypes.data, D.ctypes.data, ids.ctypes.data, lens.ctypes.data, wk.cap)
+            assert n >= 0
+            c2, l2 = o.trace_line(S, D)
+            compare(wk.to_paper(ids[:n].astype(np.int64)), lens[:n], c2, l2)
+            # does the line enter some cell twice (two separate runs)?
+            t = np.linspace(0, 1, 200001)
+            cells = cell_of_points(o, S[None] + t[:, None] * (D - S)[None])
+            inside = np.hypot(*(S[None, :2] + t[:, None] * (D - S)[None, :2]).T) < w.radius
+            ci = cells[inside]
+            if len(ci):
+                runs = ci[np.r_[True, np.diff(ci) != 0]]
+                reentries += len(runs) != len(set(runs.tolist()))
+        assert reentries > 10     # the merge path was exercised
