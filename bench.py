@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--workload", default="cone-256r-32v-hc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=12, help="detector rows in the oracle sample")
+    ap.add_argument("--sweeps", type=int, default=0, help="override the sweep count (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -82,7 +85,16 @@ def main():
     import synth
 
     w = synth.get(args.workload)
+    if args.sweeps:
+        w = w.with_(sweeps=args.sweeps)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     P = synth.make_projections(w)
     proj = torch.as_tensor(P, dtype=torch.float32).to(dev).contiguous()
     nc = w.remap_nc or 2 * w.n_rings

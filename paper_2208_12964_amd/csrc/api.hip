@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "trace_walk.hpp"
 #include "uspg_internal.hpp"
 
 namespace uspg {
@@ -118,10 +119,7 @@ int uspg_build_grid(const uspg_grid_desc *desc, uspg_grid **out)
     if ((rc = current_device(&g->device)) != USPG_OK) { delete g; return rc; }
     std::vector<double2> cs(g->c2d);
     for (int i = 0; i < g->nr; ++i)
-        for (int b = 0; b < g->ng[i]; ++b) {
-            double ang = b * (kTwoPi / g->ng[i]);
-            cs[g->head[i] + b] = make_double2(std::cos(ang), std::sin(ang));
-        }
+        for (int b = 0; b < g->ng[i]; ++b) cs[g->head[i] + b] = walk::boundary_dir(b, g->ng[i]);
     if ((rc = g->d_ng.alloc(sizeof(int32_t) * g->nr)) != USPG_OK ||
         (rc = g->d_head.alloc(sizeof(int64_t) * (g->nr + 1))) != USPG_OK ||
         (rc = g->d_cs.alloc(sizeof(double2) * g->c2d)) != USPG_OK) {

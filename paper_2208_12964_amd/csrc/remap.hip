@@ -14,6 +14,10 @@
 
 #include "uspg_internal.hpp"
 
+// the pixel -> cell decision is floating point deciding an integer: keep the
+// arithmetic unfused, as on the host
+#pragma clang fp contract(off)
+
 namespace uspg {
 namespace {
 

@@ -34,6 +34,12 @@ struct double2 {
 };
 #endif
 
+// Floating point decides integers here (which cell a piece lies in), so the
+// arithmetic must be the same on every compiler: no fused multiply-add.
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
+
 namespace uspg {
 namespace walk {
 
@@ -53,6 +59,31 @@ struct TraceGeo {
     double Wu, Wv, Dso, Dsd;
     double eps;
 };
+
+// Direction (cos, sin) of the lower boundary of sector b in a ring of ng
+// sectors, angle 2 pi b / ng.  Reduced to the first half quadrant so that
+// multiples of a quarter turn are exact and mirror-symmetric boundaries get
+// mirror-symmetric values.
+inline double2 boundary_dir(int b, int ng)
+{
+    long q4 = (4L * b) / ng;            // quadrant
+    long rem = 4L * b - q4 * ng;        // angle (pi/2) rem / ng inside it
+    double c, s;
+    if (2 * rem <= ng) {
+        double t = (kTwoPiW / 4) * (double)rem / ng;
+        c = std::cos(t); s = std::sin(t);
+    } else {
+        double t = (kTwoPiW / 4) * (double)(ng - rem) / ng;
+        c = std::sin(t); s = std::cos(t);
+    }
+    if (rem == 0) { c = 1.0; s = 0.0; }
+    switch (q4 & 3) {
+    case 0: return double2{c, s};
+    case 1: return double2{-s, c};
+    case 2: return double2{-c, -s};
+    default: return double2{s, -c};
+    }
+}
 
 struct Entry {
     uint32_t id;
@@ -128,7 +159,7 @@ struct Ray {
 USPG_HD inline double sq(double x) { return x * x; }
 
 // View-0 source and detector point of ray `ray` (scan description).
-USPG_HD void ray_points(const TraceGeo &G, int64_t ray, double *S, double *D)
+USPG_HD inline void ray_points(const TraceGeo &G, int64_t ray, double *S, double *D)
 {
     if (G.geom == kParallel2D) {
         double t = -G.Wu + (ray + 0.5) * (2.0 * G.Wu / G.U);
@@ -289,7 +320,7 @@ struct Walker {
 
 // Chord of the line from S towards D through the disk / cylinder; false if
 // it misses.
-USPG_HD bool setup_line(const TraceGeo &G, const double *S, const double *D, Ray &ray)
+USPG_HD inline bool setup_line(const TraceGeo &G, const double *S, const double *D, Ray &ray)
 {
     ray.S[0] = S[0]; ray.S[1] = S[1]; ray.S[2] = S[2];
     ray.e[0] = D[0] - ray.S[0];
@@ -322,7 +353,7 @@ USPG_HD bool setup_line(const TraceGeo &G, const double *S, const double *D, Ray
 }
 
 // View-0 ray `r` of the scan.
-USPG_HD bool setup_ray(const TraceGeo &G, int64_t r, Ray &ray)
+USPG_HD inline bool setup_ray(const TraceGeo &G, int64_t r, Ray &ray)
 {
     double S[3], D[3];
     ray_points(G, r, S, D);

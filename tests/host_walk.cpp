@@ -47,10 +47,7 @@ int hw_setup(int nr, int nz, double R, double H, const int32_t *ng, int q, int g
     }
     st.cs.resize(st.head[nr]);
     for (int i = 0; i < nr; ++i)
-        for (int b = 0; b < ng[i]; ++b) {
-            double ang = b * (kTwoPiW / ng[i]);
-            st.cs[st.head[i] + b] = double2{std::cos(ang), std::sin(ang)};
-        }
+        for (int b = 0; b < ng[i]; ++b) st.cs[st.head[i] + b] = boundary_dir(b, ng[i]);
     TraceGeo &G = st.G;
     G.nr = nr; G.nz = nz; G.is3d = is3d; G.geom = geom;
     G.R = R; G.r = R / nr; G.H = H; G.h = nz > 1 || H > 0 ? H / nz : 0.0; G.z0 = -H / 2;
