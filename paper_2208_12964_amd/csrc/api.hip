@@ -194,20 +194,21 @@ int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *sc, void *stream
     c->scan = *sc;
     c->device = g->device;
     c->q = q;
+    c->grp = kRingGroup;
     c->kq.resize(g->nr);
     c->hq.resize(g->nr + 1);
-    c->hq[0] = 0;
-    for (int i = 0; i < g->nr; ++i) {
-        c->kq[i] = g->ng[i] / q;
-        c->hq[i + 1] = c->hq[i] + c->kq[i];
-    }
-    c->Cq = c->hq[g->nr];
+    c->Cq = walk::wedge_tables(g->nr, g->ng.data(), q, c->grp, c->kq.data(), c->hq.data(), nullptr);
+    c->hq[g->nr] = (int32_t)c->Cq;
+    c->ring_of_off.assign(c->Cq, -1);
+    walk::wedge_tables(g->nr, g->ng.data(), q, c->grp, c->kq.data(), c->hq.data(), c->ring_of_off.data());
     c->Wc = (int64_t)g->nz * c->Cq;
     c->Wtot = q * c->Wc;
+    if (c->Wtot >= (int64_t)1 << 31) {
+        delete c;
+        return fail(USPG_E_ARG, "device image layout exceeds 2^31 cells");
+    }
     c->nrays = (int64_t)sc->det_u * sc->det_v;
-    std::vector<int32_t> ring_of(c->Cq);
-    for (int i = 0; i < g->nr; ++i)
-        for (int b = 0; b < c->kq[i]; ++b) ring_of[c->hq[i] + b] = i;
+    const std::vector<int32_t> &ring_of = c->ring_of_off;
     hipStream_t s = (hipStream_t)stream;
     if ((rc = c->d_kq.alloc(sizeof(int32_t) * g->nr)) != USPG_OK ||
         (rc = c->d_hq.alloc(sizeof(int32_t) * (g->nr + 1))) != USPG_OK ||
@@ -271,9 +272,9 @@ int uspg_coeffs_row(const uspg_coeffs *c, int32_t view, int64_t ray, int64_t *ce
     for (int j = 0; j < len; ++j) {
         int64_t x = ((int64_t)ids[j] + (int64_t)view * c->Wc) % c->Wtot;
         int64_t aw = x / c->Wc, rem = x % c->Wc, k = rem / c->Cq, o = rem % c->Cq;
-        int i = 0;
-        while (i + 1 < g->nr && c->hq[i + 1] <= o) ++i;
-        int64_t s = aw * c->kq[i] + (o - c->hq[i]);
+        int i = c->ring_of_off[o];
+        if (i < 0) return fail(USPG_E_INTERNAL, "row entry in layout padding");
+        int64_t s = aw * c->kq[i] + (o - c->hq[i]) / c->grp;
         cells[j] = k * g->c2d + g->head[i] + s;
     }
     return USPG_OK;
@@ -302,7 +303,7 @@ size_t uspg_mart_workspace_bytes(const uspg_coeffs *c, int32_t dtype, double tol
 {
     if (!c) return 0;
     size_t sz = dtype == USPG_F64 ? sizeof(double) : sizeof(float);
-    size_t n = (size_t)c->g->ncells * sz;
+    size_t n = (size_t)c->Wtot * sz;
     return tol > 0 ? 2 * n + 16 : n;
 }
 

@@ -70,7 +70,7 @@ bool lattice_ok(const std::vector<uint8_t> &mark, int U, int V, int ku, int kv)
 int colour_reference_view(uspg_coeffs *c, hipStream_t s)
 {
     const int U = c->scan.det_u, V = c->scan.det_v;
-    const int64_t ncells = c->g->ncells, nrays = c->nrays;
+    const int64_t ncells = c->Wtot, nrays = c->nrays;   // ids live in the device layout
     uint32_t *cnt = nullptr, *cptr = nullptr, *rays = nullptr;
     uint8_t *mark = nullptr;
     int rc = USPG_OK;

@@ -11,7 +11,7 @@
 //   load ids / coefficients (coalesced), rotate ids, gather f,
 //   Pbar = sum a f and a_max by wavefront reductions (fixed order),
 //   c = beta (P / Pbar - 1) / a_max,  f_j <- f_j (1 + c a_j)   (eq. 18).
-// Rows up to 64 * NCH coefficients stay in registers between the gather and
+// Rows up to 64 * 16 coefficients stay in registers between the gather and
 // the scatter; longer rows are re-read in a second pass.
 #include "uspg_internal.hpp"
 
@@ -63,7 +63,70 @@ __device__ inline int xcd_block(int b, int nb)
     return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
-template <class T, class TC, int NCH>
+// One row of C chunks of 64 coefficients, kept in registers.  Indices are
+// clamped and coefficients masked instead of branching, so every load of a
+// phase is issued before the first wait: the ids and coefficients, then all
+// gathers, then the reductions, then the predicated scatter.
+template <class T, class TC, int C>
+__device__ __forceinline__ void row_in_registers(const BatchArgs<T, TC> &A, const uint32_t *ids,
+                                                 const TC *a, int n, T P, int lane)
+{
+    uint32_t id[C];
+    T av[C], fv[C];
+    const int last = n - 1;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int j = lane + 64 * k;
+        const int jj = j < n ? j : last;
+        // the coefficient stream is read once per view: non-temporal loads
+        // keep it from evicting the image from the caches
+        const uint32_t t = __builtin_nontemporal_load(ids + jj) + A.shift;
+        id[k] = t >= A.wtot ? t - A.wtot : t;
+        av[k] = (T)__builtin_nontemporal_load(a + jj) * (j < n ? T(1) : T(0));   // masked, not branched
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) fv[k] = A.f[id[k]];
+    T acc = T(0), amax = T(0);
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        acc += av[k] * fv[k];
+        amax = av[k] > amax ? av[k] : amax;
+    }
+    acc = wave_sum(acc);
+    amax = wave_max(amax);
+    if (!(acc > T(0)) || !(amax > T(0))) return;
+    const T c = A.beta * (P / acc - T(1)) / amax;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        if (lane + 64 * k < n) A.f[id[k]] = fv[k] * (T(1) + c * av[k]);
+    }
+}
+
+// Rows longer than the register path: forward pass, then re-read and update.
+template <class T, class TC>
+__device__ void row_streamed(const BatchArgs<T, TC> &A, const uint32_t *ids, const TC *a, int n, T P,
+                             int lane)
+{
+    T acc = T(0), amax = T(0);
+    for (int j = lane; j < n; j += 64) {
+        uint32_t t = ids[j] + A.shift;
+        t = t >= A.wtot ? t - A.wtot : t;
+        T av = (T)a[j];
+        acc += av * A.f[t];
+        amax = av > amax ? av : amax;
+    }
+    acc = wave_sum(acc);
+    amax = wave_max(amax);
+    if (!(acc > T(0)) || !(amax > T(0))) return;
+    const T c = A.beta * (P / acc - T(1)) / amax;
+    for (int j = lane; j < n; j += 64) {
+        uint32_t t = ids[j] + A.shift;
+        t = t >= A.wtot ? t - A.wtot : t;
+        A.f[t] = A.f[t] * (T(1) + c * (T)a[j]);
+    }
+}
+
+template <class T, class TC, int MAXC>
 __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
 {
     const int lane = threadIdx.x & 63;
@@ -77,60 +140,24 @@ __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
     if (n == 0) return;
     const uint32_t *ids = A.ids + beg;
     const TC *a = A.a + beg;
-
-    if (NCH > 0 && n <= 64 * NCH) {
-        uint32_t id[NCH > 0 ? NCH : 1];
-        T av[NCH > 0 ? NCH : 1], fv[NCH > 0 ? NCH : 1];
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) {
-            const int j = lane + 64 * k;
-            id[k] = 0;
-            av[k] = T(0);
-            if (j < n) {
-                uint32_t t = ids[j] + A.shift;
-                id[k] = t >= A.wtot ? t - A.wtot : t;
-                av[k] = (T)a[j];
-            }
-        }
-        T acc = T(0), amax = T(0);
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) {
-            const int j = lane + 64 * k;
-            fv[k] = T(0);
-            if (j < n) {
-                fv[k] = A.f[id[k]];
-                acc += av[k] * fv[k];
-                amax = av[k] > amax ? av[k] : amax;
-            }
-        }
-        acc = wave_sum(acc);
-        amax = wave_max(amax);
-        if (!(acc > T(0)) || !(amax > T(0))) return;
-        const T c = A.beta * (A.P[r] / acc - T(1)) / amax;
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) {
-            const int j = lane + 64 * k;
-            if (j < n) A.f[id[k]] = fv[k] * (T(1) + c * av[k]);
-        }
+    const T P = A.P[r];
+    const int chunks = (n + 63) >> 6;   // wave-uniform
+    if (chunks > MAXC) {
+        row_streamed<T, TC>(A, ids, a, n, P, lane);
         return;
     }
-    // long rows: forward pass, then re-read and update
-    T acc = T(0), amax = T(0);
-    for (int j = lane; j < n; j += 64) {
-        uint32_t t = ids[j] + A.shift;
-        t = t >= A.wtot ? t - A.wtot : t;
-        T av = (T)a[j];
-        acc += av * A.f[t];
-        amax = av > amax ? av : amax;
-    }
-    acc = wave_sum(acc);
-    amax = wave_max(amax);
-    if (!(acc > T(0)) || !(amax > T(0))) return;
-    const T c = A.beta * (A.P[r] / acc - T(1)) / amax;
-    for (int j = lane; j < n; j += 64) {
-        uint32_t t = ids[j] + A.shift;
-        t = t >= A.wtot ? t - A.wtot : t;
-        A.f[t] = A.f[t] * (T(1) + c * (T)a[j]);
+    switch (chunks) {
+#define USPG_ROW_CASE(C)                                                                 \
+    case C:                                                                              \
+        if (C <= MAXC) row_in_registers<T, TC, (C <= MAXC ? C : 1)>(A, ids, a, n, P, lane); \
+        break;
+        USPG_ROW_CASE(1) USPG_ROW_CASE(2) USPG_ROW_CASE(3) USPG_ROW_CASE(4)
+        USPG_ROW_CASE(5) USPG_ROW_CASE(6) USPG_ROW_CASE(7) USPG_ROW_CASE(8)
+        USPG_ROW_CASE(9) USPG_ROW_CASE(10) USPG_ROW_CASE(11) USPG_ROW_CASE(12)
+        USPG_ROW_CASE(13) USPG_ROW_CASE(14) USPG_ROW_CASE(15) USPG_ROW_CASE(16)
+#undef USPG_ROW_CASE
+    default:
+        break;
     }
 }
 
@@ -138,33 +165,40 @@ __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
 struct LayoutArgs {
     const int32_t *ring_of_off, *kq, *hq;
     const int64_t *head;
-    uint32_t Cq, Wc, c2d, ncells;
+    uint32_t Cq, Wc, c2d, wtot, grp;
 };
 
-__device__ inline uint32_t native_to_paper(uint32_t x, const LayoutArgs &L)
+// Paper index of device index x, or -1 for a padding slot of the layout.
+__device__ inline int64_t native_to_paper(uint32_t x, const LayoutArgs &L)
 {
     uint32_t aw = x / L.Wc;
     uint32_t rem = x - aw * L.Wc;
     uint32_t k = rem / L.Cq;
     uint32_t o = rem - k * L.Cq;
     int i = L.ring_of_off[o];
-    uint32_t b = o - (uint32_t)L.hq[i];
+    if (i < 0) return -1;
+    uint32_t b = (o - (uint32_t)L.hq[i]) / L.grp;
     uint32_t s = aw * (uint32_t)L.kq[i] + b;
-    return k * L.c2d + (uint32_t)L.head[i] + s;
+    return (int64_t)k * L.c2d + L.head[i] + s;
 }
 
+// Padding slots are set to 1 (never touched by a ray, neutral for eq. 19).
 template <class T>
 __global__ __launch_bounds__(256) void to_native(LayoutArgs L, const T *paper, T *native)
 {
     uint32_t x = blockIdx.x * 256u + threadIdx.x;
-    if (x < L.ncells) native[x] = paper[native_to_paper(x, L)];
+    if (x >= L.wtot) return;
+    int64_t p = native_to_paper(x, L);
+    native[x] = p < 0 ? T(1) : paper[p];
 }
 
 template <class T>
 __global__ __launch_bounds__(256) void to_paper(LayoutArgs L, const T *native, T *paper)
 {
     uint32_t x = blockIdx.x * 256u + threadIdx.x;
-    if (x < L.ncells) paper[native_to_paper(x, L)] = native[x];
+    if (x >= L.wtot) return;
+    int64_t p = native_to_paper(x, L);
+    if (p >= 0) paper[p] = native[x];
 }
 
 // max_j |f_j - g_j| / g_j (eq. 19), values are positive so their bit
@@ -207,34 +241,21 @@ void launch_batch(const BatchArgs<T, TC> &A, hipStream_t s)
 template <class T, class TC>
 void launch_batch_n(int nch, const BatchArgs<T, TC> &A, hipStream_t s)
 {
-    switch (nch) {
-    case 1: launch_batch<T, TC, 1>(A, s); break;
-    case 2: launch_batch<T, TC, 2>(A, s); break;
-    case 4: launch_batch<T, TC, 4>(A, s); break;
-    case 8: launch_batch<T, TC, 8>(A, s); break;
-    case 12: launch_batch<T, TC, 12>(A, s); break;
-    case 16: launch_batch<T, TC, 16>(A, s); break;
-    default: launch_batch<T, TC, 0>(A, s); break;
-    }
+    // the instantiation bounds the register path; longer rows stream
+    if (nch <= 2) launch_batch<T, TC, 2>(A, s);
+    else if (nch <= 4) launch_batch<T, TC, 4>(A, s);
+    else if (nch <= 8) launch_batch<T, TC, 8>(A, s);
+    else launch_batch<T, TC, 16>(A, s);
 }
 
-int pick_nch(int max_row)
-{
-    if (max_row <= 64) return 1;
-    if (max_row <= 128) return 2;
-    if (max_row <= 256) return 4;
-    if (max_row <= 512) return 8;
-    if (max_row <= 768) return 12;
-    if (max_row <= 1024) return 16;
-    return 0;
-}
+int pick_nch(int max_row) { return (max_row + 63) / 64; }
 
 template <class T, class TC>
 int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_sweeps, double beta,
               double tol, int32_t *sweeps_done, hipStream_t s)
 {
     const uspg_grid *g = c->g;
-    const uint32_t ncells = (uint32_t)g->ncells;
+    const uint32_t ncells = (uint32_t)c->Wtot;   // device layout, padded
     T *nat = static_cast<T *>(work);
     T *old = tol > 0 ? nat + ncells : nullptr;
     using UB = typename Bits<T>::U;
@@ -245,7 +266,8 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
     L.kq = c->d_kq.as<int32_t>();
     L.hq = c->d_hq.as<int32_t>();
     L.head = g->d_head.as<int64_t>();
-    L.Cq = (uint32_t)c->Cq; L.Wc = (uint32_t)c->Wc; L.c2d = (uint32_t)g->c2d; L.ncells = ncells;
+    L.Cq = (uint32_t)c->Cq; L.Wc = (uint32_t)c->Wc; L.c2d = (uint32_t)g->c2d; L.wtot = ncells;
+    L.grp = (uint32_t)c->grp;
     const unsigned pb = (ncells + 255) / 256;
     hipLaunchKernelGGL(to_native<T>, dim3(pb), dim3(256), 0, s, L, image, nat);
 

@@ -74,7 +74,7 @@ int trace_reference_view(uspg_coeffs *c, hipStream_t s)
     G.cs = g->d_cs.as<double2>();
     G.kq = c->d_kq.as<int32_t>();
     G.hq = c->d_hq.as<int32_t>();
-    G.Cq = c->Cq; G.Wc = c->Wc;
+    G.Cq = c->Cq; G.Wc = c->Wc; G.grp = c->grp;
     G.U = sc.det_u; G.V = sc.det_v;
     G.Wu = sc.det_half_u; G.Wv = sc.det_half_v; G.Dso = sc.src_axis; G.Dsd = sc.src_det;
     G.eps = 1e-12 * g->R;

@@ -55,10 +55,49 @@ struct TraceGeo {
     const double2 *cs;
     const int32_t *kq, *hq;
     int64_t Cq, Wc;
+    int grp;          // rings per group of the blocked in-plane layout
     int U, V;
     double Wu, Wv, Dso, Dsd;
     double eps;
 };
+
+// Device (wedge-major, ring-group blocked) image layout.
+//
+// With q view steps per turn, ring i holds k_i = n_g(i) / q sectors per
+// wedge.  Inside one (wedge, slice) the rings are taken in groups of `grp`;
+// a group is stored sector-major, ring-minor, padded to the group's largest
+// k_i:  cell (i, b) sits at hq_i + b * grp, hq_i = group base + (i mod grp).
+// So one 128-byte line holds 32 / grp sectors of grp neighbouring rings, and
+// a line crossing rings radially stays in one line for up to grp cells.
+// Whole image: wedge a, slice k at a * Wc + k * Cq, Wc = Nz * Cq; rotating
+// by v views adds v * Wc modulo q * Wc.  Padding cells belong to no cell of
+// the grid.  ring_of_off[o] is the ring of within-slice offset o, -1 for
+// padding.  Returns Cq.
+inline int64_t wedge_tables(int nr, const int32_t *ng, int q, int grp, int32_t *kq, int32_t *hq,
+                            int32_t *ring_of_off /* may be null */)
+{
+    int64_t base = 0;
+    for (int g0 = 0; g0 < nr; g0 += grp) {
+        int kmax = 0;
+        for (int i = g0; i < g0 + grp && i < nr; ++i) {
+            kq[i] = ng[i] / q;
+            kmax = kq[i] > kmax ? kq[i] : kmax;
+        }
+        for (int i = g0; i < g0 + grp && i < nr; ++i) {
+            hq[i] = (int32_t)(base + (i - g0));
+            if (ring_of_off) {
+                for (int b = 0; b < kmax; ++b)
+                    ring_of_off[base + (int64_t)b * grp + (i - g0)] = b < kq[i] ? i : -1;
+            }
+        }
+        if (ring_of_off) {
+            for (int j = nr - g0; j < grp; ++j)   // missing rings of a short last group
+                for (int b = 0; b < kmax; ++b) ring_of_off[base + (int64_t)b * grp + j] = -1;
+        }
+        base += (int64_t)grp * kmax;
+    }
+    return base;
+}
 
 // Direction (cos, sin) of the lower boundary of sector b in a ring of ng
 // sectors, angle 2 pi b / ng.  Reduced to the first half quadrant so that
@@ -190,7 +229,7 @@ struct Walker {
         int kqi = G.kq[i];
         int aw = s / kqi;
         int b = s - aw * kqi;
-        return (uint32_t)(aw * G.Wc + (int64_t)k * G.Cq + G.hq[i] + b);
+        return (uint32_t)(aw * G.Wc + (int64_t)k * G.Cq + G.hq[i] + (int64_t)b * G.grp);
     }
 
     USPG_HD void next_plane()

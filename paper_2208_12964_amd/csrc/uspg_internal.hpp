@@ -51,16 +51,18 @@ struct uspg_grid {
 // Coefficient handle: reference-view rows in the device (wedge-major) cell
 // numbering, lattice colouring and the tables of the wedge layout.
 //
-// Wedge-major layout: with q view steps per turn and k_i = n_g(i) / q sectors
-// of ring i per wedge, sector s = a k_i + b of ring i in slice k is stored at
-//     a * Wc + k * Cq + hq_i + b,   Cq = sum_i k_i,  Wc = Nz * Cq,
-// so rotating by v view steps adds v * Wc modulo q * Wc.
+// Device image layout (trace_walk.hpp, wedge_tables): sector s = a k_i + b of
+// ring i in slice k is stored at a * Wc + k * Cq + hq_i + b * grp, so
+// rotating by v view steps adds v * Wc modulo Wtot = q * Wc (>= cells: the
+// ring groups are padded).
 struct uspg_coeffs {
     const uspg_grid *g = nullptr;
     uspg_scan_desc scan{};
     int device = 0;
     int q = 0;
     std::vector<int32_t> kq, hq;  // per ring
+    std::vector<int32_t> ring_of_off;  // per within-slice offset (-1: padding)
+    int grp = 1;
     int64_t Cq = 0, Wc = 0, Wtot = 0;
     int64_t nrays = 0, nnz = 0;
     int32_t max_row = 0;
@@ -70,12 +72,14 @@ struct uspg_coeffs {
     uspg::DevBuf ids;             // uint32 [nnz]
     uspg::DevBuf a;               // float or double [nnz]
     uspg::DevBuf d_kq, d_hq;      // int32 [nr]
-    uspg::DevBuf d_ring_of_off;   // int32 [Cq]: ring of each within-wedge offset
+    uspg::DevBuf d_ring_of_off;   // int32 [Cq]: ring of each within-slice offset, -1 padding
     int64_t device_bytes = 0;
 };
 
 namespace uspg {
 
+// Rings per group of the blocked device layout.
+constexpr int kRingGroup = 4;
 
 // trace.hip
 int trace_reference_view(uspg_coeffs *c, hipStream_t s);

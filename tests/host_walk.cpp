@@ -12,7 +12,7 @@ using namespace uspg::walk;
 namespace {
 
 struct State {
-    std::vector<int32_t> ng, kq, hq;
+    std::vector<int32_t> ng, kq, hq, ring_of;
     std::vector<int64_t> head;
     std::vector<double2> cs;
     TraceGeo G{};
@@ -30,9 +30,10 @@ struct Capture {
 
 extern "C" {
 
-// Grid and scan of the walk; q = view steps per turn (must divide every ng).
+// Grid and scan of the walk; q = view steps per turn (must divide every ng);
+// grp = rings per group of the device layout.
 int hw_setup(int nr, int nz, double R, double H, const int32_t *ng, int q, int geom, int is3d, int U,
-             int V, double Wu, double Wv, double Dso, double Dsd)
+             int V, double Wu, double Wv, double Dso, double Dsd, int grp)
 {
     st = State();
     st.ng.assign(ng, ng + nr);
@@ -42,9 +43,11 @@ int hw_setup(int nr, int nz, double R, double H, const int32_t *ng, int q, int g
     for (int i = 0; i < nr; ++i) {
         if (ng[i] % q) return -2;
         st.head[i + 1] = st.head[i] + ng[i];
-        st.kq[i] = ng[i] / q;
-        st.hq[i + 1] = st.hq[i] + st.kq[i];
     }
+    int64_t cq = wedge_tables(nr, ng, q, grp, st.kq.data(), st.hq.data(), nullptr);
+    st.hq[nr] = (int32_t)cq;
+    st.ring_of.assign(cq, -1);
+    wedge_tables(nr, ng, q, grp, st.kq.data(), st.hq.data(), st.ring_of.data());
     st.cs.resize(st.head[nr]);
     for (int i = 0; i < nr; ++i)
         for (int b = 0; b < ng[i]; ++b) st.cs[st.head[i] + b] = boundary_dir(b, ng[i]);
@@ -53,7 +56,7 @@ int hw_setup(int nr, int nz, double R, double H, const int32_t *ng, int q, int g
     G.R = R; G.r = R / nr; G.H = H; G.h = nz > 1 || H > 0 ? H / nz : 0.0; G.z0 = -H / 2;
     G.ng = st.ng.data(); G.head = st.head.data(); G.cs = st.cs.data();
     G.kq = st.kq.data(); G.hq = st.hq.data();
-    G.Cq = st.hq[nr]; G.Wc = (int64_t)nz * G.Cq;
+    G.Cq = st.hq[nr]; G.Wc = (int64_t)nz * G.Cq; G.grp = grp;
     G.U = U; G.V = V; G.Wu = Wu; G.Wv = Wv; G.Dso = Dso; G.Dsd = Dsd;
     G.eps = 1e-12 * R;
     return 0;
@@ -76,6 +79,15 @@ static int walk_row(Ray &r, uint32_t *ids, double *lens, int cap)
     Walker<RowSink<true, double>> w(st.G, r, fill);
     w.run();
     return fill.count == n ? n : -1;
+}
+
+// Layout tables: kq, hq (nr entries each) and ring_of_off (Cq entries).
+int64_t hw_tables(int32_t *kq, int32_t *hq, int32_t *ring_of)
+{
+    for (size_t i = 0; i < st.kq.size(); ++i) { kq[i] = st.kq[i]; hq[i] = st.hq[i]; }
+    if (ring_of)
+        for (size_t o = 0; o < st.ring_of.size(); ++o) ring_of[o] = st.ring_of[o];
+    return (int64_t)st.ring_of.size();
 }
 
 int hw_trace(int64_t ray, uint32_t *ids, double *lens, int cap)

@@ -26,23 +26,35 @@ def hw():
                     "-Wno-unknown-pragmas", os.path.join(HERE, "host_walk.cpp"), "-o", so], check=True)
     L = C.CDLL(so)
     L.hw_setup.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_int, C.c_int,
-                           C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
+                           C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                           C.c_int]
     L.hw_trace.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int]
+    L.hw_tables.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.hw_tables.restype = C.c_int64
     return L
 
 
+# rings per group of the library's device layout (uspg_internal.hpp kRingGroup)
+GROUP = 4
+
+
 class Walk:
-    def __init__(self, L, w, o):
+    def __init__(self, L, w, o, grp=GROUP):
         self.L, self.w, self.o = L, w, o
         q = round(w.n_views * 2 * math.pi / w.span)
-        self.q = q
+        self.q, self.grp = q, grp
         ng = np.ascontiguousarray(o.ng, dtype=np.int32)
         rc = L.hw_setup(w.n_rings, w.n_slices, w.radius, w.height, ng.ctypes.data, q, GEOM[w.geometry],
-                        int(w.is3d), w.det_u, w.det_v, w.det_half_u, w.det_half_v, w.src_axis, w.src_det)
+                        int(w.is3d), w.det_u, w.det_v, w.det_half_u, w.det_half_v, w.src_axis, w.src_det,
+                        grp)
         assert rc == 0
-        self.kq = o.ng // q
-        self.hq = np.concatenate([[0], np.cumsum(self.kq)])
-        self.Cq = int(self.hq[-1])
+        self.kq = np.zeros(w.n_rings, dtype=np.int32)
+        self.hq = np.zeros(w.n_rings, dtype=np.int32)
+        self.Cq = int(L.hw_tables(self.kq.ctypes.data, self.hq.ctypes.data, None))
+        self.ring_of = np.zeros(self.Cq, dtype=np.int32)
+        L.hw_tables(self.kq.ctypes.data, self.hq.ctypes.data, self.ring_of.ctypes.data)
+        # the layout: every grid cell has exactly one slot, the rest is padding
+        assert (self.ring_of >= 0).sum() * q == o.head[-1]
         self.Wc = w.n_slices * self.Cq
         self.cap = 8 * (w.n_rings + w.n_slices) + 64
 
@@ -57,8 +69,9 @@ class Walk:
         x = (x + view * self.Wc) % (self.q * self.Wc)
         a, rem = x // self.Wc, x % self.Wc
         k, off = rem // self.Cq, rem % self.Cq
-        i = np.searchsorted(self.hq, off, side="right") - 1
-        s = a * self.kq[i] + (off - self.hq[i])
+        i = self.ring_of[off]
+        assert np.all(i >= 0)
+        s = a * self.kq[i] + (off - self.hq[i]) // self.grp
         return k * self.o.head[-1] + self.o.head[i] + s
 
 
@@ -146,3 +159,19 @@ def test_walk_random_and_near_tangent_lines(hw):
                 runs = ci[np.r_[True, np.diff(ci) != 0]]
                 reentries += len(runs) != len(set(runs.tolist()))
         assert reentries > 10     # the merge path was exercised
+
+
+@pytest.mark.parametrize("grp", [1, 3, 8])
+def test_layout_group_size_is_a_bijection(hw, grp):
+    # any ring-group size gives the same rows once mapped back to the paper's
+    # numbering, and every grid cell has exactly one slot in the layout
+    for w in (synth.get("par2d-32r-8v"), synth.small_cone(n_rings=13, n_views=4, det=10, m=4, n_slices=5)):
+        o = Oracle(w)
+        wk = Walk(hw, w, o, grp=grp)
+        ref = Walk(hw, w, o, grp=1)
+        wk = Walk(hw, w, o, grp=grp)
+        for r in range(0, o.n_rays, 3):
+            ids, lens = wk.row(r)
+            c2, l2 = o.trace_view(0).row(r) if r == 0 else o.trace_line(*o.ray(0, r))
+            compare_rows(o, r, wk.to_paper(ids), lens, c2, l2)
+        assert ref.Cq <= wk.Cq
