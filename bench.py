@@ -23,6 +23,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "mart_batch-cone-256r-32v-hc.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2208_12964_amd", "csrc", "mart.hip")
+
+
+def counter_traffic():
+    """HBM bytes per mart_batch launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+    the kernel source changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(PROFILE):
+        return None
+    fields = {}
+    for line in open(PROFILE):
+        if ":" in line and line.startswith("- `"):
+            key, val = line[3:].split("`", 1)
+            fields[key] = val.split(":", 1)[1].strip().strip("`")
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if fields.get("source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -32,7 +52,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cone-256r-32v-hc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=12, help="detector rows in the oracle sample")
+    ap.add_argument("--cpu-rows", type=int, default=20, help="detector rows in the oracle sample")
     ap.add_argument("--sweeps", type=int, default=0, help="override the sweep count (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
@@ -119,11 +139,13 @@ def main():
         step()
     torch.cuda.synchronize()
     rec = []
+    U.mart_timing(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         img, cart, co, grid = step(rec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    batch_ms, batch_launches = U.mart_timing(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     nnz, lattice = rec[0][1], rec[0][2]
     updates = w.n_views * nnz * w.sweeps
@@ -131,9 +153,11 @@ def main():
     mart_ms = np.mean([r[0][1].elapsed_time(r[0][2]) for r in rec])
     remap_ms = np.mean([r[0][2].elapsed_time(r[0][3]) for r in rec])
     n_launch = w.sweeps * w.n_views * lattice[0] * lattice[1]
-    per_launch_s = mart_ms * 1e-3 / n_launch
+    assert batch_launches == n_launch * args.steps
+    per_launch_s = batch_ms * 1e-3 / batch_launches
     bytes_per_launch = 16.0 * updates / n_launch
     achieved = bytes_per_launch / per_launch_s / 1e9
+    traffic = counter_traffic()
     f = img.float().cpu().numpy()
     out = {
         "metric": "MART ray-cell updates/s", "value": updates / (ms_step * 1e-3), "unit": "updates/s",
@@ -146,7 +170,8 @@ def main():
         "sweeps_per_s": w.sweeps / (mart_ms * 1e-3),
         "phases_ms": {"build": build_ms, "mart": mart_ms, "remap": remap_ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
                      "kernel": "mart_batch", "bytes_per_update": 16,
                      "launches_per_step": n_launch, "avg_launch_us": per_launch_s * 1e6},
         "image": {"min": float(f.min()), "max": float(f.max())},

@@ -176,6 +176,15 @@ int mart_run(const uspg_coeffs *c, int32_t dtype, const void *proj, void *image,
              size_t work_bytes, int32_t n_sweeps, double beta, double tol,
              int32_t *sweeps_done, void *stream);
 
+/* Timing of mart_run's batch kernels (profiling aid).  enable = 1 resets the
+ * accumulators and turns timing on: every later mart_run records one HIP
+ * event pair on its stream around its sequence of (view, class) batch
+ * kernels (nothing between them), synchronises the stream at its end and
+ * adds the elapsed time and the number of batch launches.  enable = 0 turns
+ * timing off.  batch_ms and batch_launches (host, nullable) receive the
+ * totals so far.  Process-wide; not meant for concurrent mart_run calls. */
+int uspg_mart_timing(int32_t enable, double *batch_ms, int64_t *batch_launches);
+
 /* ---- USPG -> Cartesian grid (Sec. II.B) -----------------------------------
  * cart: device [n_slices][nc][nc]; pixel (ix, iy) covers the square of side
  * 2R/nc centred at ((2 ix + 1 - nc) R / nc, (2 iy + 1 - nc) R / nc).

@@ -72,10 +72,11 @@ def lib():
     L.uspg_mart_workspace_bytes.restype = SZ
     L.mart_run.argtypes = [P, I32, P, P, P, SZ, I32, D, D, P, P]
     L.uspg_to_cartesian.argtypes = [P, I32, P, P, I32, I32, P]
+    L.uspg_mart_timing.argtypes = [I32, P, P]
     L.uspg_last_error.restype = C.c_char_p
     for name in ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_build_coeffs",
                  "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "mart_run",
-                 "uspg_to_cartesian"):
+                 "uspg_to_cartesian", "uspg_mart_timing"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -233,10 +234,18 @@ def to_cartesian(grid: Grid, image: torch.Tensor, nc: int, mode: str = "point",
     return out
 
 
+def mart_timing(enable: bool):
+    """Turn batch-kernel timing of mart_run on (resets) or off; returns
+    (batch_ms, batch_launches) accumulated so far."""
+    ms, n = C.c_double(), C.c_int64()
+    _check(lib().uspg_mart_timing(1 if enable else 0, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
 EXPORTED = ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_free_grid",
             "uspg_build_coeffs", "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts",
             "uspg_free_coeffs", "uspg_mart_workspace_bytes", "mart_run", "uspg_to_cartesian",
-            "uspg_last_error")
+            "uspg_last_error", "uspg_mart_timing")
 
 
 def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, colour=(0, 0),
@@ -252,5 +261,5 @@ def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, co
     return image, cart, grid, coeffs
 
 
-__all__ = ["Grid", "Coeffs", "mart", "to_cartesian", "reconstruct", "USPGError", "lib", "LIB_PATH",
+__all__ = ["Grid", "Coeffs", "mart", "mart_timing", "to_cartesian", "reconstruct", "USPGError", "lib", "LIB_PATH",
            "EXPORTED", "math"]

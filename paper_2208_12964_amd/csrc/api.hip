@@ -320,6 +320,11 @@ int mart_run(const uspg_coeffs *c, int32_t dtype, const void *proj, void *image,
     return mart_launch(c, dtype, proj, image, work, n_sweeps, beta, tol, sweeps_done, (hipStream_t)stream);
 }
 
+int uspg_mart_timing(int32_t enable, double *batch_ms, int64_t *batch_launches)
+{
+    return mart_timing(enable, batch_ms, batch_launches);
+}
+
 int uspg_to_cartesian(const uspg_grid *g, int32_t dtype, const void *image, void *cart, int32_t nc,
                       int32_t mode, void *stream)
 {

@@ -13,6 +13,8 @@
 //   c = beta (P / Pbar - 1) / a_max,  f_j <- f_j (1 + c a_j)   (eq. 18).
 // Rows up to 64 * 16 coefficients stay in registers between the gather and
 // the scatter; longer rows are re-read in a second pass.
+#include <atomic>
+
 #include "uspg_internal.hpp"
 
 namespace uspg {
@@ -250,6 +252,11 @@ void launch_batch_n(int nch, const BatchArgs<T, TC> &A, hipStream_t s)
 
 int pick_nch(int max_row) { return (max_row + 63) / 64; }
 
+// Batch-kernel timing (uspg_mart_timing).
+std::atomic<int> g_timing{0};
+std::atomic<int64_t> g_timing_launches{0};
+std::atomic<int64_t> g_timing_ns{0};
+
 template <class T, class TC>
 int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_sweeps, double beta,
               double tol, int32_t *sweeps_done, hipStream_t s)
@@ -283,6 +290,14 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
     const int nch = pick_nch(c->max_row);
     const int K = c->Ku * c->Kv;
     int done = 0;
+    const bool timing = g_timing.load() != 0 && tol == 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int64_t launches = 0;
+    if (timing) {
+        USPG_HIP(hipEventCreate(&ev0));
+        USPG_HIP(hipEventCreate(&ev1));
+        USPG_HIP(hipEventRecord(ev0, s));
+    }
     for (int sw = 0; sw < n_sweeps; ++sw) {
         if (tol > 0) USPG_HIP(hipMemcpyAsync(old, nat, sizeof(T) * ncells, hipMemcpyDeviceToDevice, s));
         for (int v = 0; v < c->scan.n_views; ++v) {
@@ -297,6 +312,7 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
                 A.nblk = (A.ncls + kWaves - 1) / kWaves;
                 if (A.ncls == 0) continue;
                 launch_batch_n<T, TC>(nch, A, s);
+                ++launches;
             }
         }
         USPG_HIP(hipGetLastError());
@@ -313,6 +329,16 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
             if ((double)hv <= tol) break;
         }
     }
+    if (timing) {
+        USPG_HIP(hipEventRecord(ev1, s));
+        USPG_HIP(hipEventSynchronize(ev1));
+        float ms = 0.f;
+        USPG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        g_timing_ns += (int64_t)((double)ms * 1e6);
+        g_timing_launches += launches;
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
     hipLaunchKernelGGL(to_paper<T>, dim3(pb), dim3(256), 0, s, L, nat, image);
     USPG_HIP(hipGetLastError());
     if (sweeps_done) *sweeps_done = done;
@@ -320,6 +346,18 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
 }
 
 }  // namespace
+
+int mart_timing(int enable, double *batch_ms, int64_t *batch_launches)
+{
+    if (enable) {
+        g_timing_ns = 0;
+        g_timing_launches = 0;
+    }
+    g_timing = enable ? 1 : 0;
+    if (batch_ms) *batch_ms = (double)g_timing_ns.load() * 1e-6;
+    if (batch_launches) *batch_launches = g_timing_launches.load();
+    return USPG_OK;
+}
 
 int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work,
                 int n_sweeps, double beta, double tol, int32_t *sweeps_done, hipStream_t s)

@@ -91,6 +91,7 @@ int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t
 // mart.hip
 int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work,
                 int n_sweeps, double beta, double tol, int32_t *sweeps_done, hipStream_t s);
+int mart_timing(int enable, double *batch_ms, int64_t *batch_launches);
 // remap.hip
 int remap_launch(const uspg_grid *g, int dtype, const void *image, void *cart, int nc, int mode,
                  hipStream_t s);
