@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cone-256r-32v-hc")
+    ap.add_argument("--mode", default="single", choices=["single", "batch2d", "serve"],
+                    help="single: the 256-ring cone path (default); batch2d: 64 mixed 2D slices "
+                         "one at a time vs one persistent launch; serve: the request loop")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=20, help="detector rows in the oracle sample")
     ap.add_argument("--sweeps", type=int, default=0, help="override the sweep count (profiling runs)")
@@ -92,8 +95,76 @@ def cpu_baseline(w, lattice, P, rows):
                       f"{t2 - t1:.2f} s, FP64"}
 
 
+def bench_batch2d(args):
+    """64 independent 2D slices (ring counts 32..256, 8..32 views, 2 Nr bins,
+    15 sweeps): one mart_run per slice in sequence vs one autotuned
+    persistent launch.  value = slices reconstructed per second (batched)."""
+    import torch
+
+    import paper_2208_12964_amd as U
+    import synth
+
+    dev = torch.device("cuda:0")
+    ws = synth.batch2d_members(64)
+    t0 = time.perf_counter()
+    grids = [U.Grid.from_workload(w) for w in ws]
+    cos = [U.Coeffs.from_workload(g, w) for g, w in zip(grids, ws)]
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    projs = [torch.as_tensor(synth.make_projections(w), dtype=torch.float32, device=dev).contiguous()
+             for w in ws]
+    sweeps = [w.sweeps for w in ws]
+    betas = [w.beta for w in ws]
+    works = [torch.empty(c.workspace_bytes(), dtype=torch.uint8, device=dev) for c in cos]
+
+    def one_at_a_time():
+        out = []
+        for co, proj, g, w, wk in zip(cos, projs, grids, ws, works):
+            img = torch.ones(g.n_cells, device=dev)
+            U.mart(co, proj, img, w.sweeps, w.beta, work=wk)
+            out.append(img)
+        return out
+
+    b = U.Batch(cos)
+    ones = [torch.ones(g.n_cells, device=dev) for g in grids]
+    tune_ms = b.autotune(projs, ones, betas, probe_sweeps=1, works=works)
+
+    def batched():
+        imgs = [torch.ones(g.n_cells, device=dev) for g in grids]
+        b.run(projs, imgs, sweeps, betas, works=works)
+        return imgs
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            res = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, res
+
+    t_seq, alone = timed(one_at_a_time, max(1, args.steps))
+    t_bat, multi = timed(batched, max(1, args.steps))
+    same = all(torch.equal(a, m) for a, m in zip(alone, multi))
+    updates = sum(w.n_views * c.nnz * w.sweeps for w, c in zip(ws, cos))
+    info = b.info()
+    out = {"metric": "USPG 2D slices reconstructed/s (64 mixed slices, 15 sweeps)",
+           "value": len(ws) / t_bat, "unit": "slices/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "ms_per_step": t_bat * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batch2d-64", "rings": sorted(set(w.n_rings for w in ws)),
+                      "views": sorted(set(w.n_views for w in ws)), "sweeps": 15},
+           "one_at_a_time": {"slices_per_s": len(ws) / t_seq, "ms": t_seq * 1e3},
+           "speedup_vs_one_at_a_time": t_seq / t_bat, "bitwise_equal_to_one_at_a_time": same,
+           "updates_per_s": updates / t_bat, "autotuned": info, "autotune_probe_ms": tune_ms,
+           "build_s": build_s}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.mode == "batch2d" and args.gpus == 1:
+        return bench_batch2d(args)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(independent reconstructions shard with no communication; see the design notes).",

@@ -197,6 +197,60 @@ int uspg_mart_timing(int32_t enable, double *batch_ms, int64_t *batch_launches);
 int uspg_to_cartesian(const uspg_grid *g, int32_t dtype, const void *image, void *cart,
                       int32_t nc, int32_t mode, void *stream);
 
+/* ---- many problems run together ------------------------------------------
+ * A batch plans MART for n independent problems (each with its own grid,
+ * coefficients, projections and image) that run concurrently, each in its
+ * own MART order (sweeps > views > colour classes).  Two modes:
+ *  - lockstep (1, default): launch t performs step t, one (view, class)
+ *    batch, of every unfinished problem, each problem with as many
+ *    workgroups as its largest class needs; the whole sequence of launches
+ *    is captured once as a HIP graph (re-captured when the step count or
+ *    the launch shape changes) and replayed with one graph launch per run;
+ *  - persistent (0): one launch, one workgroup per problem for the whole
+ *    solve, with workgroup barriers between classes; a problem whose
+ *    device-layout image fits the workgroup's LDS keeps it there.
+ * Either way the result of every problem is bit for bit the one mart_run
+ * gives for it alone (same per-ray arithmetic and order).
+ * All coefficient sets must share one coefficient type and the current
+ * device.  The batch keeps pointers to the coefficient handles: they must
+ * outlive it.  Allocates a small device descriptor table. */
+typedef struct uspg_batch uspg_batch;
+
+int uspg_build_batch(int32_t n, const uspg_coeffs *const *coeffs, int32_t dtype, uspg_batch **out);
+
+/* Launch settings: mode (0 persistent, 1 lockstep), threads per workgroup
+ * (multiple of 64; 64..1024 persistent, 64..256 lockstep) and whether
+ * LDS-resident images are allowed (persistent mode).  Synchronous
+ * (re-uploads the descriptor tables). */
+int uspg_batch_set(uspg_batch *b, int32_t mode, int32_t block_threads, int32_t use_lds);
+
+/* Current settings; n_lds = problems whose image lives in LDS (persistent
+ * mode); lds_bytes = dynamic LDS per workgroup.  NULL skips. */
+int uspg_batch_info(const uspg_batch *b, int32_t *mode, int32_t *block_threads, int32_t *use_lds,
+                    int32_t *n_lds, int64_t *lds_bytes);
+
+/* Runs every problem: host arrays of n device pointers (proj[i] as for
+ * mart_run, image[i] in the paper's numbering, read as f0 and overwritten,
+ * work[i] device scratch of work_bytes[i] >= uspg_mart_workspace_bytes(coeffs
+ * [i], dtype, 0)), per-problem sweep counts and relaxation.  Fixed sweep
+ * counts only (no stopping rule).  Asynchronous on `stream` (a first run,
+ * or one with a new step count, captures the lockstep graph first).
+ * The caller must not run the same batch on two streams at once. */
+int mart_run_batch(uspg_batch *b, const void *const *proj, void *const *image, void *const *work,
+                   const size_t *work_bytes, const int32_t *n_sweeps, const double *beta, void *stream);
+
+/* Autotuner: times probe_sweeps sweeps of the batch for each candidate
+ * setting (lockstep with 128 or 256 threads per workgroup; persistent with
+ * 256, 512 or 1024 threads, with and without LDS-resident images) on
+ * scratch copies of the images made in work[i] (image[i] is only read),
+ * keeps the fastest and returns its time in *best_ms (nullable).
+ * Synchronous. */
+int uspg_batch_autotune(uspg_batch *b, const void *const *proj, const void *const *image,
+                        void *const *work, const size_t *work_bytes, int32_t probe_sweeps,
+                        const double *beta, void *stream, double *best_ms);
+
+void uspg_free_batch(uspg_batch *b);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char *uspg_last_error(void);
 

@@ -73,10 +73,18 @@ def lib():
     L.mart_run.argtypes = [P, I32, P, P, P, SZ, I32, D, D, P, P]
     L.uspg_to_cartesian.argtypes = [P, I32, P, P, I32, I32, P]
     L.uspg_mart_timing.argtypes = [I32, P, P]
+    L.uspg_build_batch.argtypes = [I32, P, I32, C.POINTER(P)]
+    L.uspg_batch_set.argtypes = [P, I32, I32, I32]
+    L.uspg_batch_info.argtypes = [P, P, P, P, P, P]
+    L.mart_run_batch.argtypes = [P, P, P, P, P, P, P, P]
+    L.uspg_batch_autotune.argtypes = [P, P, P, P, P, I32, P, P, P]
+    L.uspg_free_batch.argtypes = [P]
+    L.uspg_free_batch.restype = None
     L.uspg_last_error.restype = C.c_char_p
     for name in ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_build_coeffs",
                  "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "mart_run",
-                 "uspg_to_cartesian", "uspg_mart_timing"):
+                 "uspg_to_cartesian", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
+                 "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -242,10 +250,82 @@ def mart_timing(enable: bool):
     return ms.value, n.value
 
 
+def _ptr_array(ptrs):
+    arr = (C.c_void_p * len(ptrs))(*[C.c_void_p(int(p)) for p in ptrs])
+    return arr
+
+
+class Batch:
+    """Many independent problems in one persistent launch: ``uspg_build_batch``,
+    ``mart_run_batch``, ``uspg_batch_autotune``.  Keeps its coefficients alive."""
+
+    def __init__(self, coeffs: list, dtype=torch.float32):
+        self.coeffs = list(coeffs)
+        self.dtype = dtype
+        arr = _ptr_array([c.handle.value for c in self.coeffs])
+        h = C.c_void_p()
+        _check(lib().uspg_build_batch(len(self.coeffs), arr, DTYPE[dtype], C.byref(h)))
+        self.handle = h
+
+    def work_buffers(self, device):
+        return [torch.empty(c.workspace_bytes(self.dtype), dtype=torch.uint8, device=device)
+                for c in self.coeffs]
+
+    MODES = {"persistent": 0, "lockstep": 1}
+
+    def set(self, mode: str = "lockstep", block_threads: int = 256, use_lds: bool = True):
+        _check(lib().uspg_batch_set(self.handle, self.MODES[mode], block_threads, 1 if use_lds else 0))
+
+    def info(self):
+        md, bt, ul, nl, lb = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib().uspg_batch_info(self.handle, C.byref(md), C.byref(bt), C.byref(ul), C.byref(nl),
+                                     C.byref(lb)))
+        return {"mode": "lockstep" if md.value == 1 else "persistent", "block_threads": bt.value,
+                "use_lds": bool(ul.value), "n_lds": nl.value, "lds_bytes": lb.value}
+
+    def _args(self, projs, images, works, sweeps, betas):
+        n = len(self.coeffs)
+        assert len(projs) == len(images) == len(works) == n
+        for t in list(projs) + list(images) + list(works):
+            _dev_check(t, "batch buffer")
+        wb = (C.c_size_t * n)(*[w.numel() * w.element_size() for w in works])
+        sw = (C.c_int32 * n)(*[int(x) for x in sweeps])
+        be = (C.c_double * n)(*[float(x) for x in betas])
+        return (_ptr_array([p.data_ptr() for p in projs]), _ptr_array([i.data_ptr() for i in images]),
+                _ptr_array([w.data_ptr() for w in works]), wb, sw, be)
+
+    def run(self, projs, images, sweeps, betas, works=None, stream=None):
+        works = works if works is not None else self.work_buffers(images[0].device)
+        P, I, W, wb, sw, be = self._args(projs, images, works, sweeps, betas)
+        _check(lib().mart_run_batch(self.handle, P, I, W, wb, sw, be, C.c_void_p(_stream(stream))))
+        self._keep = (works,)
+        return works
+
+    def autotune(self, projs, images, betas, probe_sweeps: int = 1, works=None, stream=None) -> float:
+        works = works if works is not None else self.work_buffers(images[0].device)
+        P, I, W, wb, sw, be = self._args(projs, images, works, [probe_sweeps] * len(self.coeffs), betas)
+        ms = C.c_double()
+        _check(lib().uspg_batch_autotune(self.handle, P, I, W, wb, probe_sweeps, be,
+                                         C.c_void_p(_stream(stream)), C.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().uspg_free_batch(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 EXPORTED = ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_free_grid",
             "uspg_build_coeffs", "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts",
             "uspg_free_coeffs", "uspg_mart_workspace_bytes", "mart_run", "uspg_to_cartesian",
-            "uspg_last_error", "uspg_mart_timing")
+            "uspg_last_error", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
+            "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_free_batch")
 
 
 def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, colour=(0, 0),
@@ -261,5 +341,5 @@ def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, co
     return image, cart, grid, coeffs
 
 
-__all__ = ["Grid", "Coeffs", "mart", "mart_timing", "to_cartesian", "reconstruct", "USPGError", "lib", "LIB_PATH",
+__all__ = ["Grid", "Coeffs", "Batch", "mart", "mart_timing", "to_cartesian", "reconstruct", "USPGError", "lib", "LIB_PATH",
            "EXPORTED", "math"]

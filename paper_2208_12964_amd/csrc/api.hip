@@ -43,7 +43,7 @@ static int current_device(int *dev)
     return USPG_OK;
 }
 
-static int check_device(int want)
+int check_device(int want)
 {
     int dev = -1;
     int rc = current_device(&dev);

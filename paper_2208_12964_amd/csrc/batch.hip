@@ -1,0 +1,498 @@
+// Many independent reconstructions run together.
+//
+// Two modes.  LOCKSTEP (the default): launch t performs step t -- one (view,
+// colour class) batch -- of every problem at once, each problem with as many
+// workgroups as its largest class needs (one ray per wavefront); problems
+// that have finished skip out.  Kernel boundaries order the steps, so no
+// cross-workgroup synchronisation is needed inside a launch and every
+// problem gets the whole machine's worth of parallelism.  PERSISTENT: one
+// workgroup owns one problem (a 2D slice or a small volume) for the whole
+// solve: it walks sweeps > views > colour classes and, for each class, spreads
+// the class's rays over its wavefronts (one ray per wavefront, the same per-ray
+// routine as the single-problem kernel), with a workgroup barrier between
+// classes.  A problem whose device-layout image fits the workgroup's LDS keeps
+// the image there for the whole solve (loaded once, written back once);
+// larger ones work on their image in global memory (L2-resident for these
+// sizes).  The per-problem pointers travel in the kernel arguments, so a run
+// needs no host-to-device copies; the static part of each problem (its
+// reference rows and layout constants) is uploaded once when the batch is
+// built.  The autotuner times the workgroup size (the number of rays of a
+// class in flight per problem) and the LDS choice on scratch copies of the
+// images; neither changes the arithmetic, so every setting gives the same
+// bits, equal to running the problems one at a time.
+#include <algorithm>
+#include <vector>
+
+#include "mart_row.hpp"
+#include "uspg_internal.hpp"
+
+struct uspg_batch {
+    int n = 0, dtype = USPG_F32, device = 0;
+    std::vector<const uspg_coeffs *> co;
+    uspg::DevBuf d_static;
+    int mode = 1;                 // 0 persistent, 1 lockstep
+    int block = 256;              // threads per workgroup
+    int use_lds = 1;              // allow LDS-resident images
+    size_t lds_limit = 0;         // bytes of dynamic LDS a workgroup may use
+    size_t lds_bytes = 0;         // dynamic LDS of the launch
+    int maxc = 16;
+    std::vector<int> lds_mode;    // per problem
+    // lockstep
+    uspg::DevBuf d_dyn, d_wgbeg;  // per-problem run arguments, workgroup prefix
+    std::vector<int> wgbeg;       // n + 1 entries
+    void *h_dyn = nullptr;        // pinned staging for d_dyn
+    hipEvent_t dyn_copied = nullptr;
+    // the lockstep launch sequence captured as one graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_steps = -1, g_block = -1, g_grid = -1;
+};
+
+namespace uspg {
+namespace {
+
+using row::mart_row;
+
+constexpr int kMaxBatch = 96;     // problems per launch (kernel-argument space)
+
+struct ProblemStatic {
+    const int64_t *rowptr;
+    const uint32_t *ids;
+    const void *a;
+    int64_t nrays;
+    uint32_t Wc, Wtot;
+    int U, Ku, Kv, n_views, lds;
+};
+
+template <class T>
+struct ProblemDyn {
+    const T *P;
+    T *f;                 // device-layout image (caller's work buffer)
+    int sweeps;
+    T beta;
+};
+
+template <class T>
+struct MultiArgs {
+    const ProblemStatic *st;
+    int first;            // index of the first problem of this launch
+    ProblemDyn<T> dyn[kMaxBatch];
+};
+
+template <class T, class TC, int MAXC>
+__global__ void mart_multi(MultiArgs<T> A)
+{
+    extern __shared__ unsigned char smem[];
+    T *lds = reinterpret_cast<T *>(smem);
+    const ProblemStatic S = A.st[A.first + blockIdx.x];
+    const ProblemDyn<T> D = A.dyn[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const TC *a = static_cast<const TC *>(S.a);
+    if (S.lds) {
+        for (uint32_t i = threadIdx.x; i < S.Wtot; i += blockDim.x) lds[i] = D.f[i];
+        __syncthreads();
+    }
+    const int K = S.Ku * S.Kv;
+    for (int sw = 0; sw < D.sweeps; ++sw) {
+        for (int v = 0; v < S.n_views; ++v) {
+            const uint32_t shift = (uint32_t)(((uint64_t)v * S.Wc) % S.Wtot);
+            const T *Pv = D.P + (int64_t)v * S.nrays;
+            for (int c = 0; c < K; ++c) {
+                const int cu = c % S.Ku, cw = c / S.Ku;
+                const int nu = (S.U - cu + S.Ku - 1) / S.Ku;
+                const int nw = ((int)(S.nrays / S.U) - cw + S.Kv - 1) / S.Kv;
+                const int ncls = nu * nw;
+                for (int x = wave; x < ncls; x += nwaves) {
+                    const int64_t r = (int64_t)(cw + (x / nu) * S.Kv) * S.U + cu + (x % nu) * S.Ku;
+                    const int64_t beg = S.rowptr[r];
+                    const int n = (int)(S.rowptr[r + 1] - beg);
+                    if (n == 0) continue;
+                    if (S.lds)
+                        mart_row<T, TC, MAXC>(lds, shift, S.Wtot, D.beta, S.ids + beg, a + beg, n, Pv[r], lane);
+                    else
+                        mart_row<T, TC, MAXC>(D.f, shift, S.Wtot, D.beta, S.ids + beg, a + beg, n, Pv[r], lane);
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (S.lds) {
+        for (uint32_t i = threadIdx.x; i < S.Wtot; i += blockDim.x) D.f[i] = lds[i];
+    }
+}
+
+// Step `step` of every problem: workgroup b belongs to the problem whose
+// prefix range holds it; its wavefronts take that problem's rays of the
+// current (view, class) in order.
+template <class T, class TC, int MAXC>
+__global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, const ProblemDyn<T> *dyn,
+                                                     const int *wgbeg, int n, int step)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (wgbeg[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const ProblemStatic S = st[lo];
+    const ProblemDyn<T> D = dyn[lo];
+    const int K = S.Ku * S.Kv;
+    if (step >= D.sweeps * S.n_views * K) return;
+    const int c = step % K;
+    const int v = (step / K) % S.n_views;
+    const int cu = c % S.Ku, cw = c / S.Ku;
+    const int nu = (S.U - cu + S.Ku - 1) / S.Ku;
+    const int nw = ((int)(S.nrays / S.U) - cw + S.Kv - 1) / S.Kv;
+    const int x = (b - wgbeg[lo]) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (x >= nu * nw) return;
+    const int64_t r = (int64_t)(cw + (x / nu) * S.Kv) * S.U + cu + (x % nu) * S.Ku;
+    const int64_t beg = S.rowptr[r];
+    const int len = (int)(S.rowptr[r + 1] - beg);
+    if (len == 0) return;
+    const uint32_t shift = (uint32_t)(((uint64_t)v * S.Wc) % S.Wtot);
+    mart_row<T, TC, MAXC>(D.f, shift, S.Wtot, D.beta, S.ids + beg, static_cast<const TC *>(S.a) + beg, len,
+                          D.P[(int64_t)v * S.nrays + r], threadIdx.x & 63);
+}
+
+// The step sequence is captured once into a graph (per step count and launch
+// shape) and replayed with one graph launch; the run arguments it reads live
+// in d_dyn, refreshed before every replay.
+template <class T, class TC, int MAXC>
+int lockstep_typed(uspg_batch *b, int steps, hipStream_t s)
+{
+    const int grid = b->wgbeg[b->n];
+    if (!b->gexec || b->g_steps != steps || b->g_block != b->block || b->g_grid != grid) {
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->gexec = nullptr;
+        b->graph = nullptr;
+        hipStream_t cs;
+        USPG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        int rc = USPG_OK;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = fail(USPG_E_HIP, "hipStreamBeginCapture failed");
+        } else {
+            for (int t = 0; t < steps; ++t)
+                hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC>), dim3(grid), dim3(b->block), 0, cs,
+                                   b->d_static.as<ProblemStatic>(), b->d_dyn.as<ProblemDyn<T>>(),
+                                   b->d_wgbeg.as<int>(), b->n, t);
+            if (hipStreamEndCapture(cs, &b->graph) != hipSuccess ||
+                hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+                rc = fail(USPG_E_HIP, "capturing the lockstep graph failed");
+        }
+        (void)hipStreamDestroy(cs);
+        if (rc != USPG_OK) return rc;
+        b->g_steps = steps;
+        b->g_block = b->block;
+        b->g_grid = grid;
+    }
+    USPG_HIP(hipGraphLaunch(b->gexec, s));
+    return USPG_OK;
+}
+
+template <class T, class TC>
+int lockstep_maxc(uspg_batch *b, int steps, hipStream_t s)
+{
+    if (b->maxc <= 2) return lockstep_typed<T, TC, 2>(b, steps, s);
+    if (b->maxc <= 4) return lockstep_typed<T, TC, 4>(b, steps, s);
+    if (b->maxc <= 8) return lockstep_typed<T, TC, 8>(b, steps, s);
+    return lockstep_typed<T, TC, 16>(b, steps, s);
+}
+
+template <class T, class TC, int MAXC>
+int launch_typed(const uspg_batch *b, MultiArgs<T> &A, int count, hipStream_t s)
+{
+    auto k = mart_multi<T, TC, MAXC>;
+    if (b->lds_bytes > 65536)
+        USPG_HIP(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)b->lds_bytes));
+    hipLaunchKernelGGL(k, dim3(count), dim3(b->block), b->lds_bytes, s, A);
+    USPG_HIP(hipGetLastError());
+    return USPG_OK;
+}
+
+template <class T, class TC>
+int launch_maxc(const uspg_batch *b, MultiArgs<T> &A, int count, hipStream_t s)
+{
+    if (b->maxc <= 2) return launch_typed<T, TC, 2>(b, A, count, s);
+    if (b->maxc <= 4) return launch_typed<T, TC, 4>(b, A, count, s);
+    if (b->maxc <= 8) return launch_typed<T, TC, 8>(b, A, count, s);
+    return launch_typed<T, TC, 16>(b, A, count, s);
+}
+
+// Solve on device-layout images (already permuted into work[i]).
+template <class T>
+int solve_native(const uspg_batch *b, const void *const *proj, void *const *work, const int32_t *n_sweeps,
+                 const double *beta, hipStream_t s)
+{
+    MultiArgs<T> A;
+    A.st = b->d_static.as<ProblemStatic>();
+    for (int first = 0; first < b->n; first += kMaxBatch) {
+        const int count = std::min(kMaxBatch, b->n - first);
+        A.first = first;
+        for (int j = 0; j < count; ++j) {
+            A.dyn[j].P = static_cast<const T *>(proj[first + j]);
+            A.dyn[j].f = static_cast<T *>(work[first + j]);
+            A.dyn[j].sweeps = n_sweeps[first + j];
+            A.dyn[j].beta = (T)beta[first + j];
+        }
+        const bool cf64 = b->co[0]->scan.coeff_dtype == USPG_F64;
+        int rc = cf64 ? launch_maxc<T, double>(b, A, count, s) : launch_maxc<T, float>(b, A, count, s);
+        if (rc != USPG_OK) return rc;
+    }
+    return USPG_OK;
+}
+
+template <class T>
+int solve_lockstep(uspg_batch *b, const void *const *proj, void *const *work, const int32_t *n_sweeps,
+                   const double *beta, hipStream_t s)
+{
+    // the staging buffer may still feed the previous run's copy
+    USPG_HIP(hipEventSynchronize(b->dyn_copied));
+    auto *dyn = static_cast<ProblemDyn<T> *>(b->h_dyn);
+    int steps = 0;
+    for (int i = 0; i < b->n; ++i) {
+        dyn[i].P = static_cast<const T *>(proj[i]);
+        dyn[i].f = static_cast<T *>(work[i]);
+        dyn[i].sweeps = n_sweeps[i];
+        dyn[i].beta = (T)beta[i];
+        const uspg_coeffs *c = b->co[i];
+        steps = std::max(steps, n_sweeps[i] * c->scan.n_views * c->Ku * c->Kv);
+    }
+    USPG_HIP(hipMemcpyAsync(b->d_dyn.p, dyn, sizeof(ProblemDyn<T>) * b->n, hipMemcpyHostToDevice, s));
+    USPG_HIP(hipEventRecord(b->dyn_copied, s));
+    const bool cf64 = b->co[0]->scan.coeff_dtype == USPG_F64;
+    return cf64 ? lockstep_maxc<T, double>(b, steps, s) : lockstep_maxc<T, float>(b, steps, s);
+}
+
+int solve(uspg_batch *b, const void *const *proj, void *const *work, const int32_t *n_sweeps,
+          const double *beta, hipStream_t s)
+{
+    if (b->mode == 1) {
+        if (b->dtype == USPG_F64) return solve_lockstep<double>(b, proj, work, n_sweeps, beta, s);
+        return solve_lockstep<float>(b, proj, work, n_sweeps, beta, s);
+    }
+    if (b->dtype == USPG_F64) return solve_native<double>(b, proj, work, n_sweeps, beta, s);
+    return solve_native<float>(b, proj, work, n_sweeps, beta, s);
+}
+
+// Upload the static descriptors for the current LDS setting.
+int upload_static(uspg_batch *b)
+{
+    const size_t tsz = b->dtype == USPG_F64 ? sizeof(double) : sizeof(float);
+    std::vector<ProblemStatic> st(b->n);
+    b->lds_bytes = 0;
+    b->lds_mode.assign(b->n, 0);
+    int maxrow = 0;
+    for (int i = 0; i < b->n; ++i) {
+        const uspg_coeffs *c = b->co[i];
+        ProblemStatic &p = st[i];
+        p.rowptr = c->rowptr.as<int64_t>();
+        p.ids = c->ids.as<uint32_t>();
+        p.a = c->a.p;
+        p.nrays = c->nrays;
+        p.Wc = (uint32_t)c->Wc;
+        p.Wtot = (uint32_t)c->Wtot;
+        p.U = c->scan.det_u;
+        p.Ku = c->Ku;
+        p.Kv = c->Kv;
+        p.n_views = c->scan.n_views;
+        const size_t need = (size_t)c->Wtot * tsz;
+        p.lds = b->use_lds && need <= b->lds_limit;
+        b->lds_mode[i] = p.lds;
+        if (p.lds) b->lds_bytes = std::max(b->lds_bytes, need);
+        maxrow = std::max(maxrow, (int)c->max_row);
+    }
+    b->maxc = (maxrow + 63) / 64;
+    // lockstep: enough workgroups for each problem's largest class
+    const int waves = b->block / 64;
+    b->wgbeg.assign(b->n + 1, 0);
+    for (int i = 0; i < b->n; ++i) {
+        const uspg_coeffs *c = b->co[i];
+        const int64_t nu0 = (c->scan.det_u + c->Ku - 1) / c->Ku, nw0 = (c->scan.det_v + c->Kv - 1) / c->Kv;
+        b->wgbeg[i + 1] = b->wgbeg[i] + (int)((nu0 * nw0 + waves - 1) / waves);
+    }
+    if (hipMemcpy(b->d_static.p, st.data(), sizeof(ProblemStatic) * b->n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_wgbeg.p, b->wgbeg.data(), sizeof(int) * (b->n + 1), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(USPG_E_HIP, "uploading batch descriptors failed");
+    return USPG_OK;
+}
+
+int check_runs(const uspg_batch *b, const void *const *proj, void *const *image, void *const *work,
+               const size_t *work_bytes, const int32_t *n_sweeps, const double *beta)
+{
+    if (!proj || !image || !work || !work_bytes || !n_sweeps || !beta) return fail(USPG_E_ARG, "null argument");
+    for (int i = 0; i < b->n; ++i) {
+        if (!proj[i] || !image[i] || !work[i]) return fail(USPG_E_ARG, "null buffer in batch");
+        if (n_sweeps[i] < 0 || !(beta[i] > 0)) return fail(USPG_E_ARG, "n_sweeps >= 0 and beta > 0");
+        if (work_bytes[i] < uspg_mart_workspace_bytes(b->co[i], b->dtype, 0.0))
+            return fail(USPG_E_NOMEM, "work space too small");
+    }
+    return USPG_OK;
+}
+
+}  // namespace
+}  // namespace uspg
+
+using namespace uspg;
+
+extern "C" {
+
+int uspg_build_batch(int32_t n, const uspg_coeffs *const *coeffs, int32_t dtype, uspg_batch **out)
+{
+    if (!coeffs || !out || n <= 0) return fail(USPG_E_ARG, "null or empty batch");
+    if (dtype != USPG_F32 && dtype != USPG_F64) return fail(USPG_E_ARG, "dtype");
+    *out = nullptr;
+    int dev = 0;
+    USPG_HIP(hipGetDevice(&dev));
+    for (int i = 0; i < n; ++i) {
+        if (!coeffs[i]) return fail(USPG_E_ARG, "null coefficients in batch");
+        if (coeffs[i]->device != dev) return fail(USPG_E_ARG, "coefficients on another device");
+        if (coeffs[i]->scan.coeff_dtype != coeffs[0]->scan.coeff_dtype)
+            return fail(USPG_E_ARG, "all problems of a batch must share the coefficient type");
+    }
+    auto *b = new uspg_batch();
+    b->n = n;
+    b->dtype = dtype;
+    b->device = dev;
+    b->co.assign(coeffs, coeffs + n);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete b;
+        return fail(USPG_E_HIP, "hipGetDeviceProperties failed");
+    }
+    b->lds_limit = prop.sharedMemPerBlock;
+    int rc = b->d_static.alloc(sizeof(ProblemStatic) * n);
+    if (rc == USPG_OK) rc = b->d_dyn.alloc(sizeof(ProblemDyn<double>) * n);
+    if (rc == USPG_OK) rc = b->d_wgbeg.alloc(sizeof(int) * (n + 1));
+    if (rc == USPG_OK && (hipHostMalloc(&b->h_dyn, sizeof(ProblemDyn<double>) * n) != hipSuccess ||
+                          hipEventCreateWithFlags(&b->dyn_copied, hipEventDisableTiming) != hipSuccess ||
+                          hipEventRecord(b->dyn_copied, nullptr) != hipSuccess))
+        rc = fail(USPG_E_HIP, "batch staging allocation failed");
+    if (rc == USPG_OK) rc = upload_static(b);
+    if (rc != USPG_OK) {
+        uspg_free_batch(b);
+        return rc;
+    }
+    *out = b;
+    return USPG_OK;
+}
+
+int uspg_batch_info(const uspg_batch *b, int32_t *mode, int32_t *block_threads, int32_t *use_lds,
+                    int32_t *n_lds, int64_t *lds_bytes)
+{
+    if (!b) return fail(USPG_E_ARG, "null batch");
+    if (mode) *mode = b->mode;
+    if (block_threads) *block_threads = b->block;
+    if (use_lds) *use_lds = b->use_lds;
+    if (n_lds) *n_lds = (int32_t)std::count(b->lds_mode.begin(), b->lds_mode.end(), 1);
+    if (lds_bytes) *lds_bytes = (int64_t)b->lds_bytes;
+    return USPG_OK;
+}
+
+int uspg_batch_set(uspg_batch *b, int32_t mode, int32_t block_threads, int32_t use_lds)
+{
+    if (!b) return fail(USPG_E_ARG, "null batch");
+    if (mode != 0 && mode != 1) return fail(USPG_E_ARG, "mode must be 0 (persistent) or 1 (lockstep)");
+    if (block_threads < 64 || block_threads > 1024 || block_threads % 64 ||
+        (mode == 1 && block_threads > 256))
+        return fail(USPG_E_ARG, "block_threads: multiple of 64 in [64, 1024] (lockstep: <= 256)");
+    int rc = check_device(b->device);
+    if (rc != USPG_OK) return rc;
+    b->mode = mode;
+    b->block = block_threads;
+    b->use_lds = use_lds ? 1 : 0;
+    return upload_static(b);
+}
+
+int mart_run_batch(uspg_batch *b, const void *const *proj, void *const *image, void *const *work,
+                   const size_t *work_bytes, const int32_t *n_sweeps, const double *beta, void *stream)
+{
+    if (!b) return fail(USPG_E_ARG, "null batch");
+    int rc = check_runs(b, proj, image, work, work_bytes, n_sweeps, beta);
+    if (rc == USPG_OK) rc = check_device(b->device);
+    if (rc != USPG_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < b->n; ++i)
+        if ((rc = layout_permute(b->co[i], b->dtype, image[i], work[i], 1, s)) != USPG_OK) return rc;
+    if ((rc = solve(b, proj, work, n_sweeps, beta, s)) != USPG_OK) return rc;
+    for (int i = 0; i < b->n; ++i)
+        if ((rc = layout_permute(b->co[i], b->dtype, work[i], image[i], 0, s)) != USPG_OK) return rc;
+    return USPG_OK;
+}
+
+int uspg_batch_autotune(uspg_batch *b, const void *const *proj, const void *const *image,
+                        void *const *work, const size_t *work_bytes, int32_t probe_sweeps,
+                        const double *beta, void *stream, double *best_ms)
+{
+    if (!b || probe_sweeps <= 0) return fail(USPG_E_ARG, "null batch or probe_sweeps <= 0");
+    std::vector<int32_t> sweeps(b->n, probe_sweeps);
+    int rc = check_runs(b, proj, (void *const *)image, work, work_bytes, sweeps.data(), beta);
+    if (rc == USPG_OK) rc = check_device(b->device);
+    if (rc != USPG_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    // candidates: lockstep with 2 or 4 rays per workgroup; persistent with
+    // 256 / 512 / 1024 threads, with and without LDS-resident images
+    const int cand[][3] = {{1, 128, 0}, {1, 256, 0}, {0, 256, 1}, {0, 512, 1}, {0, 1024, 1},
+                           {0, 512, 0}};
+    double best = 1e300;
+    int best_mode = b->mode, best_block = b->block, best_lds = b->use_lds;
+    hipEvent_t e0, e1;
+    USPG_HIP(hipEventCreate(&e0));
+    USPG_HIP(hipEventCreate(&e1));
+    for (const auto &cd : cand) {
+        {
+            b->mode = cd[0];
+            b->block = cd[1];
+            b->use_lds = cd[2];
+            if ((rc = upload_static(b)) != USPG_OK) break;
+            // fresh scratch copies of the images in the device layout
+            for (int i = 0; i < b->n && rc == USPG_OK; ++i)
+                rc = layout_permute(b->co[i], b->dtype, image[i], work[i], 1, s);
+            if (rc != USPG_OK) break;
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(USPG_E_HIP, "event"); break; }
+            if ((rc = solve(b, proj, work, sweeps.data(), beta, s)) != USPG_OK) break;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(USPG_E_HIP, "event");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_mode = cd[0];
+                best_block = cd[1];
+                best_lds = cd[2];
+            }
+        }
+        if (rc != USPG_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->mode = best_mode;
+    b->block = best_block;
+    b->use_lds = best_lds;
+    int rc2 = upload_static(b);
+    if (rc != USPG_OK) return rc;
+    if (best_ms) *best_ms = best;
+    return rc2;
+}
+
+void uspg_free_batch(uspg_batch *b)
+{
+    if (!b) return;
+    if (b->dyn_copied) {
+        (void)hipEventSynchronize(b->dyn_copied);
+        (void)hipEventDestroy(b->dyn_copied);
+    }
+    if (b->h_dyn) (void)hipHostFree(b->h_dyn);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->d_static.release();
+    b->d_dyn.release();
+    b->d_wgbeg.release();
+    delete b;
+}
+
+}  // extern "C"

@@ -15,32 +15,18 @@
 // the scatter; longer rows are re-read in a second pass.
 #include <atomic>
 
+#include "mart_row.hpp"
 #include "uspg_internal.hpp"
 
 namespace uspg {
 namespace {
 
+using row::mart_row;
+using row::wave_max;
+using row::wave_sum;
+
 constexpr int kWaves = 4;             // wavefronts per workgroup
 constexpr int kBlock = 64 * kWaves;
-
-template <class T>
-__device__ inline T wave_sum(T v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-template <class T>
-__device__ inline T wave_max(T v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        T o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
 
 template <class T, class TC>
 struct BatchArgs {
@@ -65,69 +51,6 @@ __device__ inline int xcd_block(int b, int nb)
     return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
-// One row of C chunks of 64 coefficients, kept in registers.  Indices are
-// clamped and coefficients masked instead of branching, so every load of a
-// phase is issued before the first wait: the ids and coefficients, then all
-// gathers, then the reductions, then the predicated scatter.
-template <class T, class TC, int C>
-__device__ __forceinline__ void row_in_registers(const BatchArgs<T, TC> &A, const uint32_t *ids,
-                                                 const TC *a, int n, T P, int lane)
-{
-    uint32_t id[C];
-    T av[C], fv[C];
-    const int last = n - 1;
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const int j = lane + 64 * k;
-        const int jj = j < n ? j : last;
-        // the coefficient stream is read once per view: non-temporal loads
-        // keep it from evicting the image from the caches
-        const uint32_t t = __builtin_nontemporal_load(ids + jj) + A.shift;
-        id[k] = t >= A.wtot ? t - A.wtot : t;
-        av[k] = (T)__builtin_nontemporal_load(a + jj) * (j < n ? T(1) : T(0));   // masked, not branched
-    }
-#pragma unroll
-    for (int k = 0; k < C; ++k) fv[k] = A.f[id[k]];
-    T acc = T(0), amax = T(0);
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        acc += av[k] * fv[k];
-        amax = av[k] > amax ? av[k] : amax;
-    }
-    acc = wave_sum(acc);
-    amax = wave_max(amax);
-    if (!(acc > T(0)) || !(amax > T(0))) return;
-    const T c = A.beta * (P / acc - T(1)) / amax;
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        if (lane + 64 * k < n) A.f[id[k]] = fv[k] * (T(1) + c * av[k]);
-    }
-}
-
-// Rows longer than the register path: forward pass, then re-read and update.
-template <class T, class TC>
-__device__ void row_streamed(const BatchArgs<T, TC> &A, const uint32_t *ids, const TC *a, int n, T P,
-                             int lane)
-{
-    T acc = T(0), amax = T(0);
-    for (int j = lane; j < n; j += 64) {
-        uint32_t t = ids[j] + A.shift;
-        t = t >= A.wtot ? t - A.wtot : t;
-        T av = (T)a[j];
-        acc += av * A.f[t];
-        amax = av > amax ? av : amax;
-    }
-    acc = wave_sum(acc);
-    amax = wave_max(amax);
-    if (!(acc > T(0)) || !(amax > T(0))) return;
-    const T c = A.beta * (P / acc - T(1)) / amax;
-    for (int j = lane; j < n; j += 64) {
-        uint32_t t = ids[j] + A.shift;
-        t = t >= A.wtot ? t - A.wtot : t;
-        A.f[t] = A.f[t] * (T(1) + c * (T)a[j]);
-    }
-}
-
 template <class T, class TC, int MAXC>
 __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
 {
@@ -142,25 +65,7 @@ __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
     if (n == 0) return;
     const uint32_t *ids = A.ids + beg;
     const TC *a = A.a + beg;
-    const T P = A.P[r];
-    const int chunks = (n + 63) >> 6;   // wave-uniform
-    if (chunks > MAXC) {
-        row_streamed<T, TC>(A, ids, a, n, P, lane);
-        return;
-    }
-    switch (chunks) {
-#define USPG_ROW_CASE(C)                                                                 \
-    case C:                                                                              \
-        if (C <= MAXC) row_in_registers<T, TC, (C <= MAXC ? C : 1)>(A, ids, a, n, P, lane); \
-        break;
-        USPG_ROW_CASE(1) USPG_ROW_CASE(2) USPG_ROW_CASE(3) USPG_ROW_CASE(4)
-        USPG_ROW_CASE(5) USPG_ROW_CASE(6) USPG_ROW_CASE(7) USPG_ROW_CASE(8)
-        USPG_ROW_CASE(9) USPG_ROW_CASE(10) USPG_ROW_CASE(11) USPG_ROW_CASE(12)
-        USPG_ROW_CASE(13) USPG_ROW_CASE(14) USPG_ROW_CASE(15) USPG_ROW_CASE(16)
-#undef USPG_ROW_CASE
-    default:
-        break;
-    }
+    mart_row<T, TC, MAXC>(A.f, A.shift, A.wtot, A.beta, ids, a, n, A.P[r], lane);
 }
 
 // Layout maps between the paper's numbering and the wedge-major layout.
@@ -346,6 +251,33 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
 }
 
 }  // namespace
+
+int layout_permute(const uspg_coeffs *c, int dtype, const void *src, void *dst, int to_native_layout,
+                   hipStream_t s)
+{
+    const uspg_grid *g = c->g;
+    LayoutArgs L;
+    L.ring_of_off = c->d_ring_of_off.as<int32_t>();
+    L.kq = c->d_kq.as<int32_t>();
+    L.hq = c->d_hq.as<int32_t>();
+    L.head = g->d_head.as<int64_t>();
+    L.Cq = (uint32_t)c->Cq; L.Wc = (uint32_t)c->Wc; L.c2d = (uint32_t)g->c2d; L.wtot = (uint32_t)c->Wtot;
+    L.grp = (uint32_t)c->grp;
+    const unsigned pb = (unsigned)((c->Wtot + 255) / 256);
+    if (dtype == USPG_F64) {
+        if (to_native_layout)
+            hipLaunchKernelGGL(to_native<double>, dim3(pb), dim3(256), 0, s, L, (const double *)src, (double *)dst);
+        else
+            hipLaunchKernelGGL(to_paper<double>, dim3(pb), dim3(256), 0, s, L, (const double *)src, (double *)dst);
+    } else {
+        if (to_native_layout)
+            hipLaunchKernelGGL(to_native<float>, dim3(pb), dim3(256), 0, s, L, (const float *)src, (float *)dst);
+        else
+            hipLaunchKernelGGL(to_paper<float>, dim3(pb), dim3(256), 0, s, L, (const float *)src, (float *)dst);
+    }
+    USPG_HIP(hipGetLastError());
+    return USPG_OK;
+}
 
 int mart_timing(int enable, double *batch_ms, int64_t *batch_launches)
 {

@@ -1,0 +1,126 @@
+// Per-ray Sp-MART update shared by the single-problem and batched kernels
+// (Sec. III.D, eqs. 17-18).  One wavefront handles one ray: coefficients are
+// loaded with non-temporal hints, the ids rotated to the view by one add and
+// a conditional subtract, the image gathered through `img` (global memory or
+// LDS), Pbar and a_max reduced across the wavefront in a fixed order, then
+//   f_j <- f_j (1 + beta (P / Pbar - 1) a_j / a_max).
+#pragma once
+
+#include "uspg_internal.hpp"
+
+namespace uspg {
+namespace row {
+
+template <class T>
+__device__ inline T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <class T>
+__device__ inline T wave_max(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        T o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// One row of C chunks of 64 coefficients, kept in registers.  Indices are
+// clamped and coefficients masked instead of branching, so every load of a
+// phase is issued before the first wait: the ids and coefficients, then all
+// gathers, then the reductions, then the predicated scatter.
+template <class T, class TC, int C, class Img>
+__device__ __forceinline__ void row_in_registers(Img img, uint32_t shift, uint32_t wtot, T beta,
+                                                 const uint32_t *ids, const TC *a, int n, T P, int lane)
+{
+    uint32_t id[C];
+    T av[C], fv[C];
+    const int last = n - 1;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int j = lane + 64 * k;
+        const int jj = j < n ? j : last;
+        // the coefficient stream is read once per view: non-temporal loads
+        // keep it from evicting the image from the caches
+        const uint32_t t = __builtin_nontemporal_load(ids + jj) + shift;
+        id[k] = t >= wtot ? t - wtot : t;
+        av[k] = (T)__builtin_nontemporal_load(a + jj) * (j < n ? T(1) : T(0));   // masked, not branched
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) fv[k] = img[id[k]];
+    T acc = T(0), amax = T(0);
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        acc += av[k] * fv[k];
+        amax = av[k] > amax ? av[k] : amax;
+    }
+    acc = wave_sum(acc);
+    amax = wave_max(amax);
+    if (!(acc > T(0)) || !(amax > T(0))) return;
+    const T c = beta * (P / acc - T(1)) / amax;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        if (lane + 64 * k < n) img[id[k]] = fv[k] * (T(1) + c * av[k]);
+    }
+}
+
+// Rows longer than the register path: forward pass, then re-read and update.
+template <class T, class TC, class Img>
+__device__ void row_streamed(Img img, uint32_t shift, uint32_t wtot, T beta, const uint32_t *ids,
+                             const TC *a, int n, T P, int lane)
+{
+    T acc = T(0), amax = T(0);
+    for (int j = lane; j < n; j += 64) {
+        uint32_t t = ids[j] + shift;
+        t = t >= wtot ? t - wtot : t;
+        T av = (T)a[j];
+        acc += av * img[t];
+        amax = av > amax ? av : amax;
+    }
+    acc = wave_sum(acc);
+    amax = wave_max(amax);
+    if (!(acc > T(0)) || !(amax > T(0))) return;
+    const T c = beta * (P / acc - T(1)) / amax;
+    for (int j = lane; j < n; j += 64) {
+        uint32_t t = ids[j] + shift;
+        t = t >= wtot ? t - wtot : t;
+        img[t] = img[t] * (T(1) + c * (T)a[j]);
+    }
+}
+
+// One ray: dispatch on its wave-uniform chunk count to a compile-time
+// unrolled register body (rows longer than 64 * MAXC are streamed).
+template <class T, class TC, int MAXC, class Img>
+__device__ __forceinline__ void mart_row(Img img, uint32_t shift, uint32_t wtot, T beta, const uint32_t *ids,
+                                         const TC *a, int n, T P, int lane)
+{
+    const int chunks = (n + 63) >> 6;   // wave-uniform
+    if (chunks > MAXC) {
+        row_streamed<T, TC>(img, shift, wtot, beta, ids, a, n, P, lane);
+        return;
+    }
+    switch (chunks) {
+#define USPG_ROW_CASE(C)                                                                          \
+    case C:                                                                                       \
+        if (C <= MAXC)                                                                            \
+            row_in_registers<T, TC, (C <= MAXC ? C : 1)>(img, shift, wtot, beta, ids, a, n, P, lane); \
+        break;
+        USPG_ROW_CASE(1) USPG_ROW_CASE(2) USPG_ROW_CASE(3) USPG_ROW_CASE(4)
+        USPG_ROW_CASE(5) USPG_ROW_CASE(6) USPG_ROW_CASE(7) USPG_ROW_CASE(8)
+        USPG_ROW_CASE(9) USPG_ROW_CASE(10) USPG_ROW_CASE(11) USPG_ROW_CASE(12)
+        USPG_ROW_CASE(13) USPG_ROW_CASE(14) USPG_ROW_CASE(15) USPG_ROW_CASE(16)
+#undef USPG_ROW_CASE
+    default:
+        break;
+    }
+}
+
+
+
+}  // namespace row
+}  // namespace uspg

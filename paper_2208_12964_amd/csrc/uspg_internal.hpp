@@ -92,6 +92,12 @@ int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t
 int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work,
                 int n_sweeps, double beta, double tol, int32_t *sweeps_done, hipStream_t s);
 int mart_timing(int enable, double *batch_ms, int64_t *batch_launches);
+// Permute an image between the paper's numbering and the device layout
+// (to_native_layout = 1: paper -> device; 0: device -> paper).
+int layout_permute(const uspg_coeffs *c, int dtype, const void *src, void *dst, int to_native_layout,
+                   hipStream_t s);
+// api.hip
+int check_device(int want);
 // remap.hip
 int remap_launch(const uspg_grid *g, int dtype, const void *image, void *cart, int nc, int mode,
                  hipStream_t s);

@@ -1,0 +1,115 @@
+"""Many problems in one persistent launch: every problem's image equals the
+one mart_run gives for it alone (bit for bit: same per-ray arithmetic and
+order), and matches the FP64 oracle within 1e-4 (FP32) / 1e-10 (FP64);
+autotuning changes speed only."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def problems(n=10, seed=11):
+    """2D parallel-beam slices of uneven ring and view counts (2 Nr bins,
+    sector multiple 2p, half-turn scans) plus two small cone-beam volumes."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        nr = int(rng.choice([8, 16, 24, 32, 48]))
+        p = int(rng.choice([4, 8, 16]))
+        out.append(synth.parallel(f"b{k}", nr, p, 2 * nr, 2 * p, phantom="ellipses", n_objects=6,
+                                  seed=4000 + k, sweeps=int(rng.integers(3, 8)), beta=0.1, dtype="f32"))
+    out.append(synth.small_cone("bc0", n_rings=10, n_views=8, det=20, m=8, n_slices=6, sweeps=4))
+    out.append(synth.small_cone("bc1", n_rings=16, n_views=4, det=24, m=4, n_slices=10, sweeps=3))
+    return out
+
+
+@pytest.fixture(scope="module")
+def U():
+    assert torch.cuda.is_available()
+    import paper_2208_12964_amd as U
+    U.lib()
+    return U
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-10)])
+def test_batch_equals_alone_and_oracle(U, dtype, tol):
+    dev = torch.device("cuda:0")
+    ws = problems()
+    grids = [U.Grid.from_workload(w) for w in ws]
+    cos = [U.Coeffs.from_workload(g, w, dtype) for g, w in zip(grids, ws)]
+    Ps = [synth.make_projections(w) for w in ws]
+    projs = [torch.as_tensor(P, device=dev).to(dtype).contiguous() for P in Ps]
+    alone = []
+    for co, proj, w, g in zip(cos, projs, ws, grids):
+        img = torch.ones(g.n_cells, dtype=dtype, device=dev)
+        U.mart(co, proj, img, w.sweeps, w.beta)
+        alone.append(img)
+    b = U.Batch(cos, dtype)
+    for mode, block, lds in (("lockstep", 256, False), ("lockstep", 128, False),
+                             ("persistent", 256, True), ("persistent", 1024, True),
+                             ("persistent", 512, False)):
+        b.set(mode, block, lds)
+        if mode == "persistent":
+            assert (b.info()["n_lds"] > 0) == lds    # small images fit the LDS
+        imgs = [torch.ones(g.n_cells, dtype=dtype, device=dev) for g in grids]
+        b.run(projs, imgs, [w.sweeps for w in ws], [w.beta for w in ws])
+        torch.cuda.synchronize()
+        for a, m in zip(alone, imgs):
+            assert torch.equal(a, m), (mode, block, lds)
+    for w, P, img in zip(ws, Ps, alone):
+        o = Oracle(w, nthreads=NTHREADS)
+        f_ref, _, _ = o.reconstruct(P)
+        f = img.cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(f - f_ref)) / np.max(np.abs(f_ref)) <= tol, w.name
+
+
+def test_autotune_keeps_results(U):
+    dev = torch.device("cuda:0")
+    ws = problems(6, seed=5)
+    grids = [U.Grid.from_workload(w) for w in ws]
+    cos = [U.Coeffs.from_workload(g, w) for g, w in zip(grids, ws)]
+    projs = [torch.as_tensor(synth.make_projections(w), dtype=torch.float32, device=dev) for w in ws]
+    b = U.Batch(cos)
+    imgs0 = [torch.ones(g.n_cells, device=dev) for g in grids]
+    ms = b.autotune(projs, imgs0, [w.beta for w in ws], probe_sweeps=1)
+    assert ms > 0
+    assert all(torch.all(i == 1) for i in imgs0)          # the caller's images are untouched
+    imgs = [torch.ones(g.n_cells, device=dev) for g in grids]
+    b.run(projs, imgs, [w.sweeps for w in ws], [w.beta for w in ws])
+    for co, proj, w, g, m in zip(cos, projs, ws, grids, imgs):
+        img = torch.ones(g.n_cells, device=dev)
+        U.mart(co, proj, img, w.sweeps, w.beta)
+        assert torch.equal(img, m)
+
+
+def test_graph_replays_match_eager(U):
+    # the lockstep sequence is one captured graph: replay it several times with
+    # the program's own eager work and synchronisations in between, and check
+    # every replay against the problems solved alone
+    dev = torch.device("cuda:0")
+    ws = problems(8, seed=3)
+    grids = [U.Grid.from_workload(w) for w in ws]
+    cos = [U.Coeffs.from_workload(g, w) for g, w in zip(grids, ws)]
+    projs = [torch.as_tensor(synth.make_projections(w), dtype=torch.float32, device=dev) for w in ws]
+    b = U.Batch(cos)
+    b.set("lockstep", 256)
+    works = b.work_buffers(dev)
+    for rep in range(4):
+        sweeps = [w.sweeps + (rep % 2) for w in ws]          # step count changes -> re-capture
+        imgs = [torch.ones(g.n_cells, device=dev) for g in grids]
+        b.run(projs, imgs, sweeps, [w.beta for w in ws], works=works)
+        junk = torch.randn(1 << 20, device=dev).sum()        # eager work between replays
+        torch.cuda.synchronize()
+        for co, proj, g, w, s_, m in zip(cos, projs, grids, ws, sweeps, imgs):
+            img = torch.ones(g.n_cells, device=dev)
+            U.mart(co, proj, img, s_, w.beta)
+            assert torch.equal(img, m), rep
+        assert torch.isfinite(junk)
