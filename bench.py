@@ -59,6 +59,15 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=0, help="override the sweep count (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=120.0, help="serve: arrival window (s)")
+    ap.add_argument("--budget-gib", type=float, default=16.0, help="serve: admission budget (GiB)")
+    ap.add_argument("--steps-per-call", type=int, default=64, help="serve: engine steps per call")
+    ap.add_argument("--lanes", default="rings", choices=["rings", "one"],
+                    help="serve: one engine per ring count, or a single engine")
+    ap.add_argument("--slots", default="256:2,128:8,64:32",
+                    help="serve: slots per lane as lane:count pairs (lane = ring count with --lanes rings)")
+    ap.add_argument("--fifo", action="store_true", help="serve: also run the one-at-a-time baseline")
     return ap.parse_args()
 
 
@@ -161,10 +170,92 @@ def bench_batch2d(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """The serving loop on the seeded Poisson stream of cone-beam requests:
+    grids and coefficients of the nine geometries built and resident first,
+    every request's projections generated in device memory before the clock
+    starts, then requests served as they arrive.  value = completed requests
+    per second (first arrival to last completion); p50 / p99 latency =
+    completion minus arrival."""
+    import torch
+
+    import paper_2208_12964_amd as U
+    import synth
+    from paper_2208_12964_amd.serve import Request, Server, serve_fifo
+
+    dev = torch.device("cuda:0")
+    items = synth.serve_trace(rate=args.rate, duration=args.duration)
+    say = lambda m: print(m, file=sys.stderr, flush=True)   # noqa: E731
+    say(f"serve: {len(items)} requests over {args.duration:.0f} s at {args.rate}/s")
+    t0 = time.perf_counter()
+    geo, rays = {}, {}
+    for key in sorted({it.key for it in items}):
+        w = synth.serve_request(0, key[0], key[1], 1)
+        g = U.Grid.from_workload(w)
+        geo[key] = (g, U.Coeffs.from_workload(g, w))
+        rays[key] = synth.scan_rays_torch(w, dev)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    coeff_bytes = sum(c.device_bytes for _, c in geo.values())
+    say(f"serve: {len(geo)} geometries built in {build_s:.1f} s ({coeff_bytes / 2**30:.2f} GiB resident)")
+    t0 = time.perf_counter()
+    projs = []
+    for i, it in enumerate(items):
+        projs.append(synth.make_projections_torch(it.workload(), dev, torch.float32, rays=rays[it.key])
+                     .reshape(-1))
+        if i % 400 == 399:
+            torch.cuda.synchronize()
+            say(f"serve: generated {i + 1} projection sets")
+    rays.clear()
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    lane_of = (lambda key: key[0]) if args.lanes == "rings" else (lambda key: 0)
+
+    def make(_items):
+        return [Request(it.k, it.arrival, it.key, pr, it.sweeps, 0.1) for it, pr in zip(items, projs)]
+
+    # warm-up: one short request per geometry through the engine
+    warm = Server(geo.get, budget=1 << 62, lane_of=lane_of)
+    warm.run([Request(-1 - j, 0.0, key, projs[next(i for i, it in enumerate(items) if it.key == key)], 1, 0.1)
+              for j, key in enumerate(sorted(geo))])
+    warm.close()
+    budget = int(args.budget_gib * 2**30)
+    slots = {int(a): int(b) for a, b in (x.split(":") for x in args.slots.split(",") if x)}
+    srv = Server(geo.get, budget=budget, lane_of=lane_of, max_slots=slots, steps_per_call=args.steps_per_call,
+                 keep_results=False)
+    reqs = make(items)
+    report = lambda st: say("serve: t=%.0f s completed %d queued %d active %d" % (   # noqa: E731
+        st["wall_s"], st["completed"], st.get("queued", 0), st.get("active", 0)))
+    st = srv.run(reqs, progress=report)
+    srv.close()
+    updates = sum(it.sweeps * it.n_views * geo[it.key][1].nnz for it in items)
+    out = {"metric": "served cone-beam reconstructions/s (Poisson 20/s, 120 s, Nr in {64,128,256}, "
+                     "p in {8,16,32}, 10-20 sweeps)",
+           "value": st["req_per_s"], "unit": "req/s", "n_gpus": 1, "steps": st["completed"], "warmup": len(geo),
+           "ms_per_step": st["wall_s"] * 1e3 / max(1, st["completed"]), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "serve-poisson", "rate_per_s": args.rate, "duration_s": args.duration,
+                      "requests": len(items), "budget_gib": args.budget_gib, "lanes": args.lanes,
+                      "slots": args.slots,
+                      "steps_per_call": args.steps_per_call},
+           "latency": {k: v for k, v in st.items() if k.endswith("_s") or k.endswith("_by_key_s")},
+           "completed": st["completed"], "rejected": st["rejected"],
+           "updates_per_s_while_serving": updates / st["wall_s"],
+           "build_s": build_s, "input_generation_s": gen_s, "coeff_gib_resident": coeff_bytes / 2**30}
+    if args.fifo:
+        say("serve: one-at-a-time baseline")
+        fst = serve_fifo(geo.get, make(items), keep_results=False,
+                         progress=lambda s: say("fifo: t=%.0f s completed %d" % (s["wall_s"], s["completed"])))
+        out["one_at_a_time"] = fst
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.mode == "batch2d" and args.gpus == 1:
         return bench_batch2d(args)
+    if args.mode == "serve" and args.gpus == 1:
+        return bench_serve(args)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(independent reconstructions shard with no communication; see the design notes).",

@@ -251,6 +251,56 @@ int uspg_batch_autotune(uspg_batch *b, const void *const *proj, const void *cons
 
 void uspg_free_batch(uspg_batch *b);
 
+/* ---- continuous batching --------------------------------------------------
+ * An engine runs MART for problems that arrive and leave at any time, the
+ * serving form of the lockstep batch above.  A problem is admitted into a
+ * free slot between step calls and starts at the engine's current step;
+ * every uspg_engine_step call advances every admitted problem by n_steps
+ * steps (one step = one (view, colour class) batch of Sec. III.D, in the
+ * problem's own sweep > view > class order), with one launch per step
+ * covering all of them.  A problem finishes after n_sweeps full sweeps;
+ * the result of each problem is bit for bit the one mart_run gives for it
+ * alone, whatever else shares the engine.
+ * max_slots bounds the problems admitted at once; dtype is the image type
+ * (USPG_F32 / USPG_F64), coeff_dtype the coefficient type every admitted
+ * coefficient set must have.  Calls on one engine use one stream and one
+ * thread; the engine lives on the device current at creation.  Allocates
+ * small device descriptor tables and a pinned staging buffer. */
+typedef struct uspg_engine uspg_engine;
+
+int uspg_engine_create(int32_t max_slots, int32_t dtype, int32_t coeff_dtype, uspg_engine **out);
+
+/* Admits one problem: proj (device, n_views x rays as for mart_run), image
+ * (device, the paper's numbering, read as f0 and overwritten with the
+ * result when the problem finishes), work (device scratch of work_bytes >=
+ * uspg_mart_workspace_bytes(c, dtype, 0), holding the problem's image
+ * while it runs).  c, proj, image and work must stay valid until the step
+ * call that reports the slot finished has completed on the stream.
+ * Enqueues the layout permutation on `stream`; *slot receives the slot id
+ * (nullable).  E_NOMEM when every slot is taken or work is too small;
+ * E_ARG for null pointers, n_sweeps <= 0, beta <= 0 or a coefficient type
+ * other than the engine's. */
+int uspg_engine_admit(uspg_engine *e, const uspg_coeffs *c, const void *proj, void *image, void *work,
+                      size_t work_bytes, int32_t n_sweeps, double beta, void *stream, int32_t *slot);
+
+/* Enqueues n_steps steps of every admitted problem on `stream`, then for
+ * every problem that has completed its sweeps enqueues the copy of its
+ * result into its image and frees its slot.  finished (host, nullable,
+ * room for cap ids) receives the freed slot ids, *n_finished their count
+ * (which may exceed cap).  The results are ready once the stream reaches
+ * this point.  Waits on the host only for the previous call's descriptor
+ * upload. */
+int uspg_engine_step(uspg_engine *e, int32_t n_steps, void *stream, int32_t *finished, int32_t cap,
+                     int32_t *n_finished);
+
+/* Problems currently admitted and steps run so far (nullable outputs). */
+int uspg_engine_info(const uspg_engine *e, int32_t *active, int64_t *global_step);
+
+/* Waits for the engine's own uploads and frees it.  Problems still
+ * admitted are dropped: their images keep f0, their work buffers hold a
+ * partial solve.  The caller synchronizes `stream` before freeing buffers. */
+void uspg_engine_destroy(uspg_engine *e);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char *uspg_last_error(void);
 

@@ -80,11 +80,18 @@ def lib():
     L.uspg_batch_autotune.argtypes = [P, P, P, P, P, I32, P, P, P]
     L.uspg_free_batch.argtypes = [P]
     L.uspg_free_batch.restype = None
+    L.uspg_engine_create.argtypes = [I32, I32, I32, C.POINTER(P)]
+    L.uspg_engine_admit.argtypes = [P, P, P, P, P, SZ, I32, D, P, P]
+    L.uspg_engine_step.argtypes = [P, I32, P, P, I32, P]
+    L.uspg_engine_info.argtypes = [P, P, P]
+    L.uspg_engine_destroy.argtypes = [P]
+    L.uspg_engine_destroy.restype = None
     L.uspg_last_error.restype = C.c_char_p
     for name in ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_build_coeffs",
                  "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "mart_run",
                  "uspg_to_cartesian", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
-                 "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune"):
+                 "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_engine_create",
+                 "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -321,11 +328,73 @@ class Batch:
             pass
 
 
+class Engine:
+    """Continuous batching: ``uspg_engine_create`` / ``_admit`` / ``_step`` /
+    ``_info`` / ``_destroy``.  Problems enter free slots between step calls
+    and leave when their sweeps are done; each result equals ``mart`` run
+    alone.  Holds references to every admitted problem's tensors and
+    coefficients until its slot is reported finished."""
+
+    def __init__(self, max_slots: int, dtype=torch.float32, coeff_dtype=None):
+        self.dtype = dtype
+        self.max_slots = max_slots
+        h = C.c_void_p()
+        _check(lib().uspg_engine_create(max_slots, DTYPE[dtype], DTYPE[coeff_dtype or dtype], C.byref(h)))
+        self.handle = h
+        self._held = {}
+        self._fin = (C.c_int32 * max_slots)()
+
+    def admit(self, coeffs: Coeffs, proj: torch.Tensor, image: torch.Tensor, n_sweeps: int, beta: float,
+              work: torch.Tensor | None = None, stream=None) -> int:
+        for t, name in ((proj, "proj"), (image, "image")):
+            _dev_check(t, name)
+        if work is None:
+            work = torch.empty(coeffs.workspace_bytes(self.dtype), dtype=torch.uint8, device=image.device)
+        _dev_check(work, "work")
+        slot = C.c_int32()
+        _check(lib().uspg_engine_admit(self.handle, coeffs.handle, C.c_void_p(proj.data_ptr()),
+                                       C.c_void_p(image.data_ptr()), C.c_void_p(work.data_ptr()),
+                                       work.numel() * work.element_size(), int(n_sweeps), float(beta),
+                                       C.c_void_p(_stream(stream)), C.byref(slot)))
+        self._held[slot.value] = (coeffs, proj, image, work)
+        return slot.value
+
+    def step(self, n_steps: int, stream=None) -> list:
+        """Advances every admitted problem; returns the slots that finished
+        (their images are final once the stream reaches this point)."""
+        nf = C.c_int32()
+        _check(lib().uspg_engine_step(self.handle, int(n_steps), C.c_void_p(_stream(stream)), self._fin,
+                                      self.max_slots, C.byref(nf)))
+        done = [self._fin[i] for i in range(nf.value)]
+        for sl in done:
+            self._held.pop(sl, None)
+        return done
+
+    def info(self):
+        a, g = C.c_int32(), C.c_int64()
+        _check(lib().uspg_engine_info(self.handle, C.byref(a), C.byref(g)))
+        return {"active": a.value, "global_step": g.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().uspg_engine_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 EXPORTED = ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_free_grid",
             "uspg_build_coeffs", "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts",
             "uspg_free_coeffs", "uspg_mart_workspace_bytes", "mart_run", "uspg_to_cartesian",
             "uspg_last_error", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
-            "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_free_batch")
+            "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_free_batch",
+            "uspg_engine_create", "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info",
+            "uspg_engine_destroy")
 
 
 def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, colour=(0, 0),
@@ -341,5 +410,5 @@ def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, co
     return image, cart, grid, coeffs
 
 
-__all__ = ["Grid", "Coeffs", "Batch", "mart", "mart_timing", "to_cartesian", "reconstruct", "USPGError", "lib", "LIB_PATH",
+__all__ = ["Grid", "Coeffs", "Batch", "Engine", "mart", "mart_timing", "to_cartesian", "reconstruct", "USPGError", "lib", "LIB_PATH",
            "EXPORTED", "math"]

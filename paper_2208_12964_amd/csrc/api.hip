@@ -43,6 +43,8 @@ static int current_device(int *dev)
     return USPG_OK;
 }
 
+int current_device_id(int *dev) { return current_device(dev); }
+
 int check_device(int want)
 {
     int dev = -1;

@@ -69,6 +69,7 @@ struct ProblemDyn {
     const T *P;
     T *f;                 // device-layout image (caller's work buffer)
     int sweeps;
+    int offset;           // lockstep: global step at which the problem starts
     T beta;
 };
 
@@ -138,9 +139,10 @@ __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, co
     const ProblemStatic S = st[lo];
     const ProblemDyn<T> D = dyn[lo];
     const int K = S.Ku * S.Kv;
-    if (step >= D.sweeps * S.n_views * K) return;
-    const int c = step % K;
-    const int v = (step / K) % S.n_views;
+    const int local = step - D.offset;
+    if (local < 0 || local >= D.sweeps * S.n_views * K) return;
+    const int c = local % K;
+    const int v = (local / K) % S.n_views;
     const int cu = c % S.Ku, cw = c / S.Ku;
     const int nu = (S.U - cu + S.Ku - 1) / S.Ku;
     const int nw = ((int)(S.nrays / S.U) - cw + S.Kv - 1) / S.Kv;
@@ -235,6 +237,7 @@ int solve_native(const uspg_batch *b, const void *const *proj, void *const *work
             A.dyn[j].P = static_cast<const T *>(proj[first + j]);
             A.dyn[j].f = static_cast<T *>(work[first + j]);
             A.dyn[j].sweeps = n_sweeps[first + j];
+            A.dyn[j].offset = 0;
             A.dyn[j].beta = (T)beta[first + j];
         }
         const bool cf64 = b->co[0]->scan.coeff_dtype == USPG_F64;
@@ -256,6 +259,7 @@ int solve_lockstep(uspg_batch *b, const void *const *proj, void *const *work, co
         dyn[i].P = static_cast<const T *>(proj[i]);
         dyn[i].f = static_cast<T *>(work[i]);
         dyn[i].sweeps = n_sweeps[i];
+        dyn[i].offset = 0;
         dyn[i].beta = (T)beta[i];
         const uspg_coeffs *c = b->co[i];
         steps = std::max(steps, n_sweeps[i] * c->scan.n_views * c->Ku * c->Kv);
@@ -277,6 +281,30 @@ int solve(uspg_batch *b, const void *const *proj, void *const *work, const int32
     return solve_native<float>(b, proj, work, n_sweeps, beta, s);
 }
 
+ProblemStatic static_of(const uspg_coeffs *c)
+{
+    ProblemStatic p;
+    p.rowptr = c->rowptr.as<int64_t>();
+    p.ids = c->ids.as<uint32_t>();
+    p.a = c->a.p;
+    p.nrays = c->nrays;
+    p.Wc = (uint32_t)c->Wc;
+    p.Wtot = (uint32_t)c->Wtot;
+    p.U = c->scan.det_u;
+    p.Ku = c->Ku;
+    p.Kv = c->Kv;
+    p.n_views = c->scan.n_views;
+    p.lds = 0;
+    return p;
+}
+
+// Workgroups of 4 wavefronts that cover a problem's largest class.
+int lockstep_groups(const uspg_coeffs *c, int waves)
+{
+    const int64_t nu0 = (c->scan.det_u + c->Ku - 1) / c->Ku, nw0 = (c->scan.det_v + c->Kv - 1) / c->Kv;
+    return (int)((nu0 * nw0 + waves - 1) / waves);
+}
+
 // Upload the static descriptors for the current LDS setting.
 int upload_static(uspg_batch *b)
 {
@@ -288,16 +316,7 @@ int upload_static(uspg_batch *b)
     for (int i = 0; i < b->n; ++i) {
         const uspg_coeffs *c = b->co[i];
         ProblemStatic &p = st[i];
-        p.rowptr = c->rowptr.as<int64_t>();
-        p.ids = c->ids.as<uint32_t>();
-        p.a = c->a.p;
-        p.nrays = c->nrays;
-        p.Wc = (uint32_t)c->Wc;
-        p.Wtot = (uint32_t)c->Wtot;
-        p.U = c->scan.det_u;
-        p.Ku = c->Ku;
-        p.Kv = c->Kv;
-        p.n_views = c->scan.n_views;
+        p = static_of(c);
         const size_t need = (size_t)c->Wtot * tsz;
         p.lds = b->use_lds && need <= b->lds_limit;
         b->lds_mode[i] = p.lds;
@@ -308,11 +327,7 @@ int upload_static(uspg_batch *b)
     // lockstep: enough workgroups for each problem's largest class
     const int waves = b->block / 64;
     b->wgbeg.assign(b->n + 1, 0);
-    for (int i = 0; i < b->n; ++i) {
-        const uspg_coeffs *c = b->co[i];
-        const int64_t nu0 = (c->scan.det_u + c->Ku - 1) / c->Ku, nw0 = (c->scan.det_v + c->Kv - 1) / c->Kv;
-        b->wgbeg[i + 1] = b->wgbeg[i] + (int)((nu0 * nw0 + waves - 1) / waves);
-    }
+    for (int i = 0; i < b->n; ++i) b->wgbeg[i + 1] = b->wgbeg[i] + lockstep_groups(b->co[i], waves);
     if (hipMemcpy(b->d_static.p, st.data(), sizeof(ProblemStatic) * b->n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_wgbeg.p, b->wgbeg.data(), sizeof(int) * (b->n + 1), hipMemcpyHostToDevice) != hipSuccess)
         return fail(USPG_E_HIP, "uploading batch descriptors failed");
@@ -330,6 +345,93 @@ int check_runs(const uspg_batch *b, const void *const *proj, void *const *image,
             return fail(USPG_E_NOMEM, "work space too small");
     }
     return USPG_OK;
+}
+
+}  // namespace
+}  // namespace uspg
+
+// Continuous-batching engine: slots hold admitted problems; every step call
+// advances all active slots through the lockstep kernel, each from the
+// global step at which it was admitted.
+struct uspg_engine {
+    int max_slots = 0, dtype = USPG_F32, coeff_dtype = USPG_F32, device = 0;
+    int64_t gstep = 0;                    // global step of the next launch
+    struct Slot {
+        bool used = false;
+        const uspg_coeffs *c = nullptr;
+        const void *proj = nullptr;
+        void *image = nullptr, *work = nullptr;
+        int sweeps = 0, total = 0, groups = 0;
+        int64_t offset = 0;
+        double beta = 0;
+    };
+    std::vector<Slot> slots;
+    std::vector<int> active;              // slot ids in launch order
+    bool dirty = true;
+    int grid = 0;
+    uspg::DevBuf d_static, d_dyn, d_wgbeg;
+    void *h_stage = nullptr;              // pinned: static, dyn, wgbeg
+    size_t stage_bytes = 0;
+    hipEvent_t staged = nullptr;
+};
+
+namespace uspg {
+namespace {
+
+constexpr int kEngineWaves = 4;
+
+template <class T>
+int engine_upload(uspg_engine *e, hipStream_t s)
+{
+    USPG_HIP(hipEventSynchronize(e->staged));
+    const int n = (int)e->active.size();
+    auto *st = static_cast<ProblemStatic *>(e->h_stage);
+    auto *dyn = reinterpret_cast<ProblemDyn<T> *>(st + e->max_slots);
+    int *wg = reinterpret_cast<int *>(dyn + e->max_slots);
+    wg[0] = 0;
+    for (int j = 0; j < n; ++j) {
+        const uspg_engine::Slot &sl = e->slots[e->active[j]];
+        st[j] = static_of(sl.c);
+        dyn[j].P = static_cast<const T *>(sl.proj);
+        dyn[j].f = static_cast<T *>(sl.work);
+        dyn[j].sweeps = sl.sweeps;
+        // steps are counted from the engine's current base so int fits
+        dyn[j].offset = (int)(sl.offset - e->gstep);
+        dyn[j].beta = (T)sl.beta;
+        wg[j + 1] = wg[j] + sl.groups;
+    }
+    e->grid = wg[n];
+    USPG_HIP(hipMemcpyAsync(e->d_static.p, st, sizeof(ProblemStatic) * n, hipMemcpyHostToDevice, s));
+    USPG_HIP(hipMemcpyAsync(e->d_dyn.p, dyn, sizeof(ProblemDyn<T>) * n, hipMemcpyHostToDevice, s));
+    USPG_HIP(hipMemcpyAsync(e->d_wgbeg.p, wg, sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
+    USPG_HIP(hipEventRecord(e->staged, s));
+    e->dirty = false;
+    return USPG_OK;
+}
+
+// Offsets were uploaded relative to the engine's step count at this call,
+// so the launches of one call are numbered from 0.
+template <class T, class TC, int MAXC>
+int engine_launch(uspg_engine *e, int steps, hipStream_t s)
+{
+    for (int t = 0; t < steps; ++t)
+        hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC>), dim3(e->grid), dim3(64 * kEngineWaves), 0, s,
+                           e->d_static.as<ProblemStatic>(), e->d_dyn.as<ProblemDyn<T>>(),
+                           e->d_wgbeg.as<int>(), (int)e->active.size(), t);
+    USPG_HIP(hipGetLastError());
+    return USPG_OK;
+}
+
+template <class T, class TC>
+int engine_maxc(uspg_engine *e, int steps, hipStream_t s)
+{
+    int64_t longest = 0;
+    for (int id : e->active) longest = std::max<int64_t>(longest, e->slots[id].c->max_row);
+    const int64_t chunks = (longest + 63) / 64;
+    if (chunks <= 2) return engine_launch<T, TC, 2>(e, steps, s);
+    if (chunks <= 4) return engine_launch<T, TC, 4>(e, steps, s);
+    if (chunks <= 8) return engine_launch<T, TC, 8>(e, steps, s);
+    return engine_launch<T, TC, 16>(e, steps, s);
 }
 
 }  // namespace
@@ -477,6 +579,123 @@ int uspg_batch_autotune(uspg_batch *b, const void *const *proj, const void *cons
     if (rc != USPG_OK) return rc;
     if (best_ms) *best_ms = best;
     return rc2;
+}
+
+int uspg_engine_create(int32_t max_slots, int32_t dtype, int32_t coeff_dtype, uspg_engine **out)
+{
+    if (!out || max_slots <= 0) return fail(USPG_E_ARG, "null output or max_slots <= 0");
+    if ((dtype != USPG_F32 && dtype != USPG_F64) || (coeff_dtype != USPG_F32 && coeff_dtype != USPG_F64))
+        return fail(USPG_E_ARG, "dtype");
+    *out = nullptr;
+    auto *e = new uspg_engine();
+    e->max_slots = max_slots;
+    e->dtype = dtype;
+    e->coeff_dtype = coeff_dtype;
+    e->slots.resize(max_slots);
+    int rc = current_device_id(&e->device);
+    e->stage_bytes = (sizeof(ProblemStatic) + sizeof(ProblemDyn<double>) + sizeof(int)) * (max_slots + 1);
+    if (rc == USPG_OK) rc = e->d_static.alloc(sizeof(ProblemStatic) * max_slots);
+    if (rc == USPG_OK) rc = e->d_dyn.alloc(sizeof(ProblemDyn<double>) * max_slots);
+    if (rc == USPG_OK) rc = e->d_wgbeg.alloc(sizeof(int) * (max_slots + 1));
+    if (rc == USPG_OK && (hipHostMalloc(&e->h_stage, e->stage_bytes) != hipSuccess ||
+                          hipEventCreateWithFlags(&e->staged, hipEventDisableTiming) != hipSuccess ||
+                          hipEventRecord(e->staged, nullptr) != hipSuccess))
+        rc = fail(USPG_E_HIP, "engine staging allocation failed");
+    if (rc != USPG_OK) {
+        uspg_engine_destroy(e);
+        return rc;
+    }
+    *out = e;
+    return USPG_OK;
+}
+
+int uspg_engine_admit(uspg_engine *e, const uspg_coeffs *c, const void *proj, void *image, void *work,
+                      size_t work_bytes, int32_t n_sweeps, double beta, void *stream, int32_t *slot)
+{
+    if (!e || !c || !proj || !image || !work) return fail(USPG_E_ARG, "null argument");
+    if (n_sweeps <= 0 || !(beta > 0)) return fail(USPG_E_ARG, "n_sweeps > 0 and beta > 0");
+    if (c->scan.coeff_dtype != e->coeff_dtype) return fail(USPG_E_ARG, "coefficient type differs from the engine's");
+    if (work_bytes < uspg_mart_workspace_bytes(c, e->dtype, 0.0)) return fail(USPG_E_NOMEM, "work space too small");
+    int rc = check_device(e->device);
+    if (rc != USPG_OK) return rc;
+    int id = -1;
+    for (int i = 0; i < e->max_slots; ++i)
+        if (!e->slots[i].used) { id = i; break; }
+    if (id < 0) return fail(USPG_E_NOMEM, "no free slot");
+    if ((rc = layout_permute(c, e->dtype, image, work, 1, (hipStream_t)stream)) != USPG_OK) return rc;
+    uspg_engine::Slot &sl = e->slots[id];
+    sl.used = true;
+    sl.c = c;
+    sl.proj = proj;
+    sl.image = image;
+    sl.work = work;
+    sl.sweeps = n_sweeps;
+    sl.total = n_sweeps * c->scan.n_views * c->Ku * c->Kv;
+    sl.groups = lockstep_groups(c, kEngineWaves);
+    sl.offset = e->gstep;
+    sl.beta = beta;
+    e->active.push_back(id);
+    e->dirty = true;
+    if (slot) *slot = id;
+    return USPG_OK;
+}
+
+int uspg_engine_step(uspg_engine *e, int32_t n_steps, void *stream, int32_t *finished, int32_t cap,
+                     int32_t *n_finished)
+{
+    if (!e || n_steps <= 0 || !n_finished) return fail(USPG_E_ARG, "null engine/output or n_steps <= 0");
+    *n_finished = 0;
+    int rc = check_device(e->device);
+    if (rc != USPG_OK) return rc;
+    if (e->active.empty()) return USPG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // step numbers inside a call start at 0: re-base the offsets every call
+    e->dirty = true;
+    rc = e->dtype == USPG_F64 ? engine_upload<double>(e, s) : engine_upload<float>(e, s);
+    if (rc != USPG_OK) return rc;
+    const bool cf64 = e->coeff_dtype == USPG_F64;
+    if (e->dtype == USPG_F64)
+        rc = cf64 ? engine_maxc<double, double>(e, n_steps, s) : engine_maxc<double, float>(e, n_steps, s);
+    else
+        rc = cf64 ? engine_maxc<float, double>(e, n_steps, s) : engine_maxc<float, float>(e, n_steps, s);
+    if (rc != USPG_OK) return rc;
+    e->gstep += n_steps;
+    std::vector<int> still;
+    for (int id : e->active) {
+        uspg_engine::Slot &sl = e->slots[id];
+        if (e->gstep - sl.offset >= sl.total) {
+            if ((rc = layout_permute(sl.c, e->dtype, sl.work, sl.image, 0, s)) != USPG_OK) return rc;
+            if (finished && *n_finished < cap) finished[*n_finished] = id;
+            ++*n_finished;
+            sl = uspg_engine::Slot();
+        } else {
+            still.push_back(id);
+        }
+    }
+    e->active.swap(still);
+    return USPG_OK;
+}
+
+int uspg_engine_info(const uspg_engine *e, int32_t *active, int64_t *global_step)
+{
+    if (!e) return fail(USPG_E_ARG, "null engine");
+    if (active) *active = (int32_t)e->active.size();
+    if (global_step) *global_step = e->gstep;
+    return USPG_OK;
+}
+
+void uspg_engine_destroy(uspg_engine *e)
+{
+    if (!e) return;
+    if (e->staged) {
+        (void)hipEventSynchronize(e->staged);
+        (void)hipEventDestroy(e->staged);
+    }
+    if (e->h_stage) (void)hipHostFree(e->h_stage);
+    e->d_static.release();
+    e->d_dyn.release();
+    e->d_wgbeg.release();
+    delete e;
 }
 
 void uspg_free_batch(uspg_batch *b)

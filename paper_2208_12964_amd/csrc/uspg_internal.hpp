@@ -98,6 +98,7 @@ int layout_permute(const uspg_coeffs *c, int dtype, const void *src, void *dst, 
                    hipStream_t s);
 // api.hip
 int check_device(int want);
+int current_device_id(int *dev);
 // remap.hip
 int remap_launch(const uspg_grid *g, int dtype, const void *image, void *cart, int nc, int mode,
                  hipStream_t s);

@@ -15,4 +15,7 @@ from .phantoms import (  # noqa: F401
     project,
     add_noise,
     make_projections,
+    make_projections_torch,
+    scan_rays_torch,
 )
+from .serving import ServeItem, serve_trace  # noqa: F401

@@ -155,3 +155,77 @@ def phantom_value(w: Workload, pts: np.ndarray) -> np.ndarray:
         q = np.sum((xr[:, :dims] / ax[:dims]) ** 2, axis=1)
         out += np.where(q <= 1.0, mu, 0.0)
     return out
+
+
+def scan_rays_torch(w: Workload, device):
+    """Ray geometry of every view with torch on `device`, in float64: the
+    source points S and directions e = D - S ([views, rays, 3]) and the
+    in-plane (2D) or full (3D) length of e ([views, rays]).  Same geometry
+    as scan_rays."""
+    import torch
+
+    f64 = torch.float64
+    U, V = w.det_u, w.det_v
+    th = torch.arange(w.n_views, dtype=f64, device=device) * (w.span / w.n_views)
+    c, s = torch.cos(th)[:, None], torch.sin(th)[:, None]       # [views, 1]
+    u = torch.arange(U, dtype=f64, device=device)
+    if w.geometry == "parallel2d":
+        t = -w.det_half_u + (u + 0.5) * (2 * w.det_half_u / U)
+        s0 = torch.stack([torch.full_like(t, -2 * w.radius), t, torch.zeros_like(t)], 1)
+        d0 = torch.stack([torch.full_like(t, 2 * w.radius), t, torch.zeros_like(t)], 1)
+    else:
+        yv = -w.det_half_u + (u + 0.5) * (2 * w.det_half_u / U)
+        if w.geometry == "cone3d":
+            zv = -w.det_half_v + (torch.arange(V, dtype=f64, device=device) + 0.5) * (2 * w.det_half_v / V)
+        else:
+            zv = torch.zeros(1, dtype=f64, device=device)
+        Z, Y = torch.meshgrid(zv, yv, indexing="ij")              # [V, U]
+        n = Y.numel()
+        s0 = torch.tensor([-w.src_axis, 0.0, 0.0], dtype=f64, device=device).expand(n, 3)
+        d0 = torch.stack([torch.full((n,), w.src_det - w.src_axis, dtype=f64, device=device),
+                          Y.reshape(-1), Z.reshape(-1)], 1)
+
+    def rot(p):   # [n, 3] -> [views, n, 3], rotation by each view angle about z
+        x, y, z = p[:, 0][None], p[:, 1][None], p[:, 2][None]
+        return torch.stack([c * x - s * y, s * x + c * y, z.expand(c.shape[0], -1)], 2)
+
+    S = rot(s0)
+    e = rot(d0) - S
+    dims = 2 if not w.is3d else 3
+    return S, e, torch.linalg.vector_norm(e[..., :dims], dim=2)
+
+
+def make_projections_torch(w: Workload, device, dtype=None, noise: bool = True, rays=None):
+    """Projection data [view][det_v][det_u] computed with torch on `device`
+    (same phantom draw, geometry and chord formula as make_projections, in
+    float64, then cast to `dtype`).  For generating many large inputs
+    directly in device memory; `rays` may pass scan_rays_torch(w, device) of
+    an equal geometry to skip rebuilding it.  Noise uses torch's generator on
+    `device` seeded with seed + 7919, so it differs from the numpy draw in
+    value but not in distribution."""
+    import torch
+
+    f64 = torch.float64
+    S, e, elen = rays if rays is not None else scan_rays_torch(w, device)
+    dims = 2 if not w.is3d else 3
+    out = torch.zeros(elen.shape, dtype=f64, device=device)
+    for cen, ax, ang, mu in draw_phantom(w):
+        ca, sa = math.cos(ang), math.sin(ang)
+        x = S - torch.as_tensor(cen, dtype=f64, device=device)
+        xr = torch.stack([ca * x[..., 0] + sa * x[..., 1], -sa * x[..., 0] + ca * x[..., 1], x[..., 2]], 2)
+        er = torch.stack([ca * e[..., 0] + sa * e[..., 1], -sa * e[..., 0] + ca * e[..., 1], e[..., 2]], 2)
+        axd = torch.as_tensor(ax[:dims], dtype=f64, device=device)
+        xs, es = xr[..., :dims] / axd, er[..., :dims] / axd
+        A = (es * es).sum(2)
+        B = (xs * es).sum(2)
+        Cq = (xs * xs).sum(2) - 1.0
+        disc = B * B - A * Cq
+        dt = torch.where(disc > 0, 2.0 * torch.sqrt(disc.clamp_min(0)) / A, torch.zeros_like(A))
+        out += mu * dt * elen
+    out = out.reshape(w.n_views, w.det_v, w.det_u)
+    if noise and w.noise > 0:
+        g = torch.Generator(device=device)
+        g.manual_seed(w.seed + 7919)
+        out = (out + w.noise * out.max() * torch.randn(out.shape, generator=g, dtype=f64, device=device)
+               ).clamp_min(0.0)
+    return out.to(dtype or f64).contiguous()
