@@ -64,6 +64,13 @@ def _load():
     lib.orc_mart.argtypes = [P, P, P, P, I, I, I, I, P, P, I, D, D, P, I]
     lib.orc_tiles_ok.argtypes = [P, P, I, I]
     lib.orc_remap.argtypes = [P, P, P, I, I]
+    lib.orc_segments_line.argtypes = [P, P, P, P, P, P, P, I, P]
+    lib.orc_segments_view.restype = I64
+    lib.orc_segments_view.argtypes = [P, P, P, P, P, P, I64, I]
+    lib.orc_rebin_view.restype = I64
+    lib.orc_rebin_view.argtypes = [P, I, P, P, P, P, P, P, P, I64, I]
+    lib.orc_rebin_conflicts.argtypes = [P, P, P, P, P, P, P, I]
+    lib.orc_mart_rebin.argtypes = [P, P, P, P, P, P, I, I, P, P, I, D, I]
     _lib = lib
     return lib
 
@@ -95,6 +102,25 @@ class CSR:
     def row(self, r: int):
         b, e = int(self.rowptr[r]), int(self.rowptr[r + 1])
         return self.cells[b:e], self.lens[b:e]
+
+
+class Segments:
+    """Segment records of the reference view (Alg. 1 steps 1-17): per ray a
+    run of (slice, ring, azimuth at entry, azimuth at exit)."""
+
+    def __init__(self, segptr, slice_, ring, phia, phib):
+        self.segptr, self.slice, self.ring, self.phia, self.phib = segptr, slice_, ring, phia, phib
+
+    @property
+    def count(self) -> int:
+        return int(self.segptr[-1])
+
+    def ray(self, r: int):
+        b, e = int(self.segptr[r]), int(self.segptr[r + 1])
+        return self.slice[b:e], self.ring[b:e], self.phia[b:e], self.phib[b:e]
+
+    def args(self):
+        return (_ptr(self.segptr), _ptr(self.slice), _ptr(self.ring), _ptr(self.phia), _ptr(self.phib))
 
 
 class Oracle:
@@ -217,6 +243,79 @@ class Oracle:
         if rc != 0:
             raise ValueError(f"orc_remap failed ({rc})")
         return cart
+
+    # -- the paper's literal variant: re-binned segment records -----------
+    def segments_line(self, S, D):
+        S = np.ascontiguousarray(S, dtype=np.float64)
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        cap = 4096
+        while True:
+            sl = np.zeros(cap, dtype=np.int32)
+            rg = np.zeros(cap, dtype=np.int32)
+            pa = np.zeros(cap)
+            pb = np.zeros(cap)
+            need = C.c_int(0)
+            n = self.lib.orc_segments_line(self._h, _ptr(S), _ptr(D), _ptr(sl), _ptr(rg), _ptr(pa), _ptr(pb),
+                                           cap, C.byref(need))
+            if n >= 0:
+                return sl[:n].copy(), rg[:n].copy(), pa[:n].copy(), pb[:n].copy()
+            cap = need.value
+
+    def segments_view(self) -> Segments:
+        segptr = np.zeros(self.n_rays + 1, dtype=np.int64)
+        ns = self.lib.orc_segments_view(self._h, _ptr(segptr), None, None, None, None, 0, self.nthreads)
+        sl = np.zeros(max(ns, 1), dtype=np.int32)
+        rg = np.zeros(max(ns, 1), dtype=np.int32)
+        pa = np.zeros(max(ns, 1))
+        pb = np.zeros(max(ns, 1))
+        got = self.lib.orc_segments_view(self._h, _ptr(segptr), _ptr(sl), _ptr(rg), _ptr(pa), _ptr(pb), ns,
+                                         self.nthreads)
+        if got != ns:
+            raise RuntimeError("orc_segments_view inconsistent")
+        return Segments(segptr, sl, rg, pa, pb)
+
+    def rebin_view(self, seg: Segments, view: int) -> CSR:
+        rowptr = np.zeros(self.n_rays + 1, dtype=np.int64)
+        nnz = self.lib.orc_rebin_view(self._h, view, *seg.args(), _ptr(rowptr), None, 0, self.nthreads)
+        cells = np.zeros(max(nnz, 1), dtype=np.int64)
+        got = self.lib.orc_rebin_view(self._h, view, *seg.args(), _ptr(rowptr), _ptr(cells), nnz, self.nthreads)
+        if got != nnz:
+            raise RuntimeError("orc_rebin_view inconsistent")
+        return CSR(rowptr, cells[:nnz], np.ones(nnz))
+
+    def rebin_conflicts(self, seg: Segments) -> np.ndarray:
+        mark = np.zeros(self.n_rays, dtype=np.uint8)
+        self.lib.orc_rebin_conflicts(self._h, *seg.args(), _ptr(mark), self.nthreads)
+        return mark.reshape(self.w.det_v, self.w.det_u)
+
+    def colour_rebin(self, seg: Segments, force=None):
+        mark = np.ascontiguousarray(self.rebin_conflicts(seg).ravel())
+        ku = C.c_int(force[0] if force else 0)
+        kv = C.c_int(force[1] if force else 0)
+        if self.lib.orc_colour(self._h, _ptr(mark), C.byref(ku), C.byref(kv)) != 0:
+            raise ValueError("lattice rejected")
+        return ku.value, kv.value
+
+    def mart_rebin(self, seg: Segments, lattice, P, f0, sweeps, beta, nthreads=None):
+        P = np.ascontiguousarray(P, dtype=np.float64).ravel()
+        f = np.array(f0, dtype=np.float64, copy=True).ravel()
+        rc = self.lib.orc_mart_rebin(self._h, *seg.args(), int(lattice[0]), int(lattice[1]), _ptr(P), _ptr(f),
+                                     int(sweeps), float(beta),
+                                     int(nthreads if nthreads is not None else self.nthreads))
+        if rc != 0:
+            raise ValueError(f"orc_mart_rebin failed ({rc})")
+        return f
+
+    def reconstruct_rebin(self, P, sweeps=None, beta=None, f0=None, lattice=None):
+        """The literal variant end to end: segment records, union colouring,
+        binary MART re-binned per view."""
+        w = self.w
+        seg = self.segments_view()
+        lat = lattice or self.colour_rebin(seg)
+        f0 = np.ones(self.n_cells) if f0 is None else f0
+        f = self.mart_rebin(seg, lat, P, f0, w.sweeps if sweeps is None else sweeps,
+                            w.beta if beta is None else beta)
+        return f, seg, lat
 
     # -- whole pipeline -----------------------------------------------------
     def reconstruct(self, P, sweeps=None, beta=None, f0=None, lattice=None, tiles=None):

@@ -243,19 +243,18 @@ static int radial_crossing(const double *S, const double *e, double alpha, doubl
     return 1;
 }
 
-/* Trace the line from S towards D through the grid.  Writes one entry per
- * traversed cell (cell id in the paper's numbering, k * C2D + H_i + s, and the
- * intersection length; 1.0 in binary mode), in order of first entry along the
- * ray.  Returns the entry count, or ORC_E_CAP if `cap` is too small (then the
- * count is stored in *need). */
-static int trace_line(const orc_t *o, const double *S, const double *D,
-                      int64_t *cells, double *lens, int cap, int *need)
+/* Breakpoints of the line S + t e (e = D - S) inside the grid (Alg. 1 steps
+ * 3-4): the chord's ends, its crossings with the cylindrical planes
+ * rho = j r (eqs. 3-4) and with the axial planes z = z0 + k h strictly
+ * inside it, sorted by distance to the source.  Returns 0 if the line
+ * misses the grid; *L is the length per unit t. */
+static int line_breakpoints(const orc_t *o, const double *S, const double *D, double *e, double *L,
+                            tvec *bp)
 {
     const int is3d = (o->geom == GEOM_CONE3D);
-    double e[3] = {D[0] - S[0], D[1] - S[1], is3d ? D[2] - S[2] : 0.0};
+    e[0] = D[0] - S[0]; e[1] = D[1] - S[1]; e[2] = is3d ? D[2] - S[2] : 0.0;
     double A = e[0] * e[0] + e[1] * e[1];          /* <S-D', S-D'> */
-    double L = sqrt(A + e[2] * e[2]);              /* length per unit t */
-    *need = 0;
+    *L = sqrt(A + e[2] * e[2]);                    /* length per unit t */
     if (A == 0.0) return 0;
 
     /* eq. 3: distance d of the XY projection S D' from the axis */
@@ -282,25 +281,42 @@ static int trace_line(const orc_t *o, const double *S, const double *D,
 
     /* Alg. 1 step 3: intersections with the cylindrical planes rho = j r and
      * the axial planes z = z0 + k h strictly inside the chord. */
-    tvec bp = {0, 0, 0};
-    tpush(&bp, t0);
-    tpush(&bp, t1);
+    tpush(bp, t0);
+    tpush(bp, t1);
     for (int j = 1; j < o->nr; ++j) {
         double rj = j * o->r;
         if (rj * rj <= d2) continue;
         double kj = sqrt((rj * rj - d2) / A);
         double ta = t - kj, tb = t + kj;
-        if (ta > t0 && ta < t1) tpush(&bp, ta);
-        if (tb > t0 && tb < t1) tpush(&bp, tb);
+        if (ta > t0 && ta < t1) tpush(bp, ta);
+        if (tb > t0 && tb < t1) tpush(bp, tb);
     }
     if (is3d && e[2] != 0.0) {
         for (int kk = 1; kk < o->nz; ++kk) {
             double tz = (o->z0 + kk * o->h - S[2]) / e[2];
-            if (tz > t0 && tz < t1) tpush(&bp, tz);
+            if (tz > t0 && tz < t1) tpush(bp, tz);
         }
     }
     /* Alg. 1 step 4: sort by distance to the source */
-    qsort(bp.t, bp.n, sizeof(double), cmp_double);
+    qsort(bp->t, bp->n, sizeof(double), cmp_double);
+    return 1;
+}
+
+/* Trace the line from S towards D through the grid.  Writes one entry per
+ * traversed cell (cell id in the paper's numbering, k * C2D + H_i + s, and the
+ * intersection length; 1.0 in binary mode), in order of first entry along the
+ * ray.  Returns the entry count, or ORC_E_CAP if `cap` is too small (then the
+ * count is stored in *need). */
+static int trace_line(const orc_t *o, const double *S, const double *D,
+                      int64_t *cells, double *lens, int cap, int *need)
+{
+    double e[3], L;
+    tvec bp = {0, 0, 0};
+    *need = 0;
+    if (!line_breakpoints(o, S, D, e, &L, &bp)) {
+        free(bp.t);
+        return 0;
+    }
 
     /* Each segment between consecutive points lies in one ring and one slice.
      * Find the sectors it crosses from the grid numbers of its end points
@@ -679,6 +695,276 @@ int orc_mart(void *h, const int64_t *rowptr, const int64_t *cells, const double 
     }
     if (done) *done = s_done;
     free(ck); free(ci); free(cs); free(fold);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The paper's literal variant: segment records re-binned per view          */
+/* (Sec. III.B-C, Alg. 1), binary coefficients, any number of views          */
+/* ------------------------------------------------------------------------ */
+
+/* Segment records of the line S -> D (Alg. 1 steps 3-14): every piece between
+ * consecutive cylinder / axial breakpoints longer than eps, in order along the
+ * line, with the slice (eq. 6) and ring (eq. 7) of its midpoint (eq. 5) and
+ * the azimuths (eq. 8) of its two end points.  No radial plane is crossed:
+ * the sectors are found per view from the azimuths.  Returns the count, or
+ * ORC_E_CAP with the count in *need. */
+static int segments_line(const orc_t *o, const double *S, const double *D, int *slice, int *ring,
+                         double *phia, double *phib, int cap, int *need)
+{
+    double e[3], L;
+    tvec bp = {0, 0, 0};
+    *need = 0;
+    if (!line_breakpoints(o, S, D, e, &L, &bp)) {
+        free(bp.t);
+        return 0;
+    }
+    int n = 0;
+    for (int q = 0; q + 1 < bp.n; ++q) {
+        double ta = bp.t[q], tb = bp.t[q + 1];
+        if ((tb - ta) * L <= o->eps) continue;
+        if (n < cap) {
+            double tm = 0.5 * (ta + tb);                               /* eq. 5 */
+            double mx = S[0] + tm * e[0], my = S[1] + tm * e[1], mz = S[2] + tm * e[2];
+            int i = (int)floor(sqrt(mx * mx + my * my) / o->r);        /* eq. 7 */
+            if (i < 0) i = 0;
+            if (i >= o->nr) i = o->nr - 1;
+            int k = 0;
+            if (o->geom == GEOM_CONE3D) {
+                k = (int)floor((mz - o->z0) / o->h);                   /* eq. 6 */
+                if (k < 0) k = 0;
+                if (k >= o->nz) k = o->nz - 1;
+            }
+            slice[n] = k;
+            ring[n] = i;
+            phia[n] = azimuth(S[0] + ta * e[0], S[1] + ta * e[1]);    /* eq. 8 */
+            phib[n] = azimuth(S[0] + tb * e[0], S[1] + tb * e[1]);
+        }
+        ++n;
+    }
+    free(bp.t);
+    *need = n;
+    return n > cap ? ORC_E_CAP : n;
+}
+
+int orc_segments_line(void *h, const double *S, const double *D, int *slice, int *ring, double *phia,
+                      double *phib, int cap, int *need)
+{
+    return segments_line((orc_t *)h, S, D, slice, ring, phia, phib, cap, need);
+}
+
+/* Segment records of every reference-view ray (segptr has rays + 1 entries;
+ * with slice == NULL only segptr is filled). */
+int64_t orc_segments_view(void *h, int64_t *segptr, int *slice, int *ring, double *phia, double *phib,
+                          int64_t cap, int nthreads)
+{
+    orc_t *o = (orc_t *)h;
+    int64_t nrays = (int64_t)o->U * o->V;
+    int *cnt = (int *)malloc(sizeof(int) * nrays);
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t r = 0; r < nrays; ++r) {
+        double S[3], D[3];
+        int need = 0;
+        orc_ray(o, 0, r, S, D);
+        segments_line(o, S, D, NULL, NULL, NULL, NULL, 0, &need);
+        cnt[r] = need;
+    }
+    segptr[0] = 0;
+    for (int64_t r = 0; r < nrays; ++r) segptr[r + 1] = segptr[r] + cnt[r];
+    free(cnt);
+    int64_t ns = segptr[nrays];
+    if (!slice) return ns;
+    if (ns > cap) return ORC_E_CAP;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t r = 0; r < nrays; ++r) {
+        double S[3], D[3];
+        int need = 0;
+        orc_ray(o, 0, r, S, D);
+        segments_line(o, S, D, slice + segptr[r], ring + segptr[r], phia + segptr[r], phib + segptr[r],
+                      (int)(segptr[r + 1] - segptr[r]), &need);
+    }
+    return ns;
+}
+
+/* Sectors of ring i met by a segment with reference azimuths pa, pb in view
+ * `view` (Alg. 1 steps 20-35).  Both azimuths advance by the source angle
+ * theta_v = v span / p and are reduced to [0, 2 pi) (reading: eq. 10 needs
+ * an angle inside the turn); eq. 10 gives the grid numbers (without the ring
+ * head).  Case 1, |phi_a - phi_b| < pi (eqs. 11-13): sectors L_h = min ..
+ * L_t = max.  Case 2 (eqs. 14-16): the segment crosses the +x axis, so the
+ * sectors run from L_h = max up to n_g - 1 and on from 0 to L_t = min.
+ * Result: first sector and count; the sectors are first, first + 1, ...
+ * modulo n_g. */
+static void rebin_segment(const orc_t *o, int view, int i, double pa, double pb, int *first, int *count)
+{
+    const double theta = view * o->span / o->p;
+    const int ng = o->ng[i];
+    const double dphi = TWO_PI / ng;                                  /* eq. 9 */
+    double a = pa + theta, b = pb + theta;                            /* step 23 */
+    if (a >= TWO_PI) a -= TWO_PI;
+    if (b >= TWO_PI) b -= TWO_PI;
+    int Ga = (int)floor(a / dphi), Gb = (int)floor(b / dphi);         /* eq. 10 */
+    if (Ga >= ng) Ga = ng - 1;
+    if (Gb >= ng) Gb = ng - 1;
+    int lo = Ga < Gb ? Ga : Gb, hi = Ga < Gb ? Gb : Ga;
+    if (fabs(a - b) < PI) {
+        *first = lo;                                                  /* eqs. 11-13 */
+        *count = hi - lo + 1;
+    } else {
+        *first = hi;                                                  /* eqs. 14-16 */
+        *count = ng - hi + lo + 1;
+    }
+}
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Binary row of one ray in view `view` from its segment records: the union
+ * of the cells (k C2D + H_i + s) of every segment's sector range, sorted
+ * ascending.  A cell met by two segments (the two passes of a line through
+ * the ring just outside the innermost ring it reaches, in one slice) counts
+ * once: a binary coefficient marks a traversed cell.  `cells` needs room for
+ * the sum of the counts.  Returns the number of distinct cells. */
+static int rebin_row(const orc_t *o, int view, int nseg, const int *slice, const int *ring,
+                     const double *phia, const double *phib, int64_t *cells)
+{
+    int n = 0;
+    for (int q = 0; q < nseg; ++q) {
+        int first, count;
+        rebin_segment(o, view, ring[q], phia[q], phib[q], &first, &count);
+        int ng = o->ng[ring[q]];
+        for (int c = 0; c < count; ++c) {
+            int sct = first + c;
+            if (sct >= ng) sct -= ng;
+            cells[n++] = (int64_t)slice[q] * o->c2d + o->head[ring[q]] + sct;
+        }
+    }
+    qsort(cells, n, sizeof(int64_t), cmp_i64);
+    int u = 0;
+    for (int q = 0; q < n; ++q)
+        if (u == 0 || cells[u - 1] != cells[q]) cells[u++] = cells[q];
+    return u;
+}
+
+static int rebin_capacity(const orc_t *o, const int64_t *segptr)
+{
+    /* a segment meets at most n_g(i) sectors of its ring */
+    int64_t nrays = (int64_t)o->U * o->V;
+    int ngmax = 0;
+    for (int i = 0; i < o->nr; ++i) ngmax = o->ng[i] > ngmax ? o->ng[i] : ngmax;
+    int64_t mx = 0;
+    for (int64_t r = 0; r < nrays; ++r) mx = segptr[r + 1] - segptr[r] > mx ? segptr[r + 1] - segptr[r] : mx;
+    return (int)(mx * ngmax + 1);
+}
+
+/* Rows of view `view` by re-binning (rowptr has rays + 1 entries; with
+ * cells == NULL only rowptr is filled). */
+int64_t orc_rebin_view(void *h, int view, const int64_t *segptr, const int *slice, const int *ring,
+                       const double *phia, const double *phib, int64_t *rowptr, int64_t *cells,
+                       int64_t cap, int nthreads)
+{
+    orc_t *o = (orc_t *)h;
+    int64_t nrays = (int64_t)o->U * o->V;
+    int rcap = rebin_capacity(o, segptr);
+    int *cnt = (int *)malloc(sizeof(int) * nrays);
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+        int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * rcap);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t r = 0; r < nrays; ++r) {
+            int64_t b = segptr[r];
+            cnt[r] = rebin_row(o, view, (int)(segptr[r + 1] - b), slice + b, ring + b, phia + b, phib + b, tmp);
+        }
+        free(tmp);
+    }
+    rowptr[0] = 0;
+    for (int64_t r = 0; r < nrays; ++r) rowptr[r + 1] = rowptr[r] + cnt[r];
+    free(cnt);
+    int64_t nnz = rowptr[nrays];
+    if (!cells) return nnz;
+    if (nnz > cap) return ORC_E_CAP;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+        int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * rcap);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t r = 0; r < nrays; ++r) {
+            int64_t b = segptr[r];
+            int n = rebin_row(o, view, (int)(segptr[r + 1] - b), slice + b, ring + b, phia + b, phib + b, tmp);
+            memcpy(cells + rowptr[r], tmp, sizeof(int64_t) * n);
+        }
+        free(tmp);
+    }
+    return nnz;
+}
+
+/* Conflict offsets of the re-binned rows: the union over all views of the
+ * offsets (du, dw) of ray pairs that share a cell in that view.  Re-binning
+ * by a rotation that is not a whole number of sectors changes which rays
+ * meet, so no single view decides; the union makes one lattice valid for
+ * every view. */
+int orc_rebin_conflicts(void *h, const int64_t *segptr, const int *slice, const int *ring,
+                        const double *phia, const double *phib, uint8_t *mark, int nthreads)
+{
+    orc_t *o = (orc_t *)h;
+    int64_t nrays = (int64_t)o->U * o->V;
+    int64_t *rowptr = (int64_t *)malloc(sizeof(int64_t) * (nrays + 1));
+    uint8_t *m1 = (uint8_t *)malloc((size_t)nrays);
+    memset(mark, 0, (size_t)nrays);
+    for (int v = 0; v < o->p; ++v) {
+        int64_t nnz = orc_rebin_view(h, v, segptr, slice, ring, phia, phib, rowptr, NULL, 0, nthreads);
+        int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * (nnz > 0 ? nnz : 1));
+        orc_rebin_view(h, v, segptr, slice, ring, phia, phib, rowptr, cells, nnz, nthreads);
+        orc_conflict_offsets(h, rowptr, cells, m1);
+        for (int64_t x = 0; x < nrays; ++x) mark[x] |= m1[x];
+        free(cells);
+    }
+    free(rowptr); free(m1);
+    return ORC_OK;
+}
+
+/* MART with binary coefficients from re-binned segment records, any number
+ * of views (Alg. 1 steps 19-38 with Sec. III.D): views ascending, then lattice
+ * classes, then the rays of a class ascending; each ray's row is rebuilt for
+ * its view and updated by eq. 18 with a_j = a_max = 1.  The lattice must come
+ * from orc_rebin_conflicts; the rays of a class then share no cell in any
+ * view, so the optional thread parallelism over a class gives the same
+ * result bit for bit. */
+int orc_mart_rebin(void *h, const int64_t *segptr, const int *slice, const int *ring, const double *phia,
+                   const double *phib, int Ku, int Kv, const double *P, double *f, int sweeps, double beta,
+                   int nthreads)
+{
+    orc_t *o = (orc_t *)h;
+    if (Ku <= 0 || Kv <= 0 || sweeps < 0) return ORC_E_ARG;
+    int64_t nrays = (int64_t)o->U * o->V;
+    int rcap = rebin_capacity(o, segptr);
+    const int K = Ku * Kv;
+    for (int sw = 0; sw < sweeps; ++sw) {
+        for (int v = 0; v < o->p; ++v) {
+            const double *Pv = P + (int64_t)v * nrays;
+            for (int c = 0; c < K; ++c) {
+                int cu = c % Ku, cw = c / Ku;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+                {
+                    int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * rcap);
+                    double *ones = (double *)malloc(sizeof(double) * rcap);
+                    for (int j = 0; j < rcap; ++j) ones[j] = 1.0;
+#pragma omp for schedule(dynamic, 16)
+                    for (int64_t r = 0; r < nrays; ++r) {
+                        int u = (int)(r % o->U), w = (int)(r / o->U);
+                        if (u % Ku != cu || w % Kv != cw) continue;
+                        int64_t b = segptr[r];
+                        int n = rebin_row(o, v, (int)(segptr[r + 1] - b), slice + b, ring + b, phia + b,
+                                          phib + b, ids);
+                        orc_mart_ray(ids, ones, n, Pv[r], f, beta);
+                    }
+                    free(ids); free(ones);
+                }
+            }
+        }
+    }
     return ORC_OK;
 }
 
