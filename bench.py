@@ -24,14 +24,22 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 PROFILE = os.path.join(ROOT, "profiles", "mart_batch-cone-256r-32v-hc.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2208_12964_amd", "csrc", "mart.hip")
+# sources of the mart_batch kernel: the launch file, then the per-ray routine
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2208_12964_amd", "csrc", f) for f in ("mart.hip", "mart_row.hpp")]
+
+
+def kernel_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def counter_traffic():
     """HBM bytes per mart_batch launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
     the kernel source changed since the counters were taken."""
-    import hashlib
     if not os.path.exists(PROFILE):
         return None
     fields = {}
@@ -39,8 +47,7 @@ def counter_traffic():
         if ":" in line and line.startswith("- `"):
             key, val = line[3:].split("`", 1)
             fields[key] = val.split(":", 1)[1].strip().strip("`")
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if fields.get("source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+    if fields.get("source_sha256") != kernel_sha256() or "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])
 

@@ -30,6 +30,14 @@ __device__ inline T wave_max(T v)
     return v;
 }
 
+// The per-ray arithmetic is pinned: explicit fused multiply-adds and no
+// compiler contraction, so every kernel that runs a row (single problem,
+// batched, persistent, engine) produces the same bits for it.
+template <class T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) { return __builtin_fma(a, b, c); }
+template <>
+__device__ __forceinline__ float fmadd<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // One row of C chunks of 64 coefficients, kept in registers.  Indices are
 // clamped and coefficients masked instead of branching, so every load of a
 // phase is issued before the first wait: the ids and coefficients, then all
@@ -38,6 +46,7 @@ template <class T, class TC, int C, class Img>
 __device__ __forceinline__ void row_in_registers(Img img, uint32_t shift, uint32_t wtot, T beta,
                                                  const uint32_t *ids, const TC *a, int n, T P, int lane)
 {
+#pragma clang fp contract(off)
     uint32_t id[C];
     T av[C], fv[C];
     const int last = n - 1;
@@ -56,7 +65,7 @@ __device__ __forceinline__ void row_in_registers(Img img, uint32_t shift, uint32
     T acc = T(0), amax = T(0);
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-        acc += av[k] * fv[k];
+        acc = fmadd(av[k], fv[k], acc);
         amax = av[k] > amax ? av[k] : amax;
     }
     acc = wave_sum(acc);
@@ -65,7 +74,7 @@ __device__ __forceinline__ void row_in_registers(Img img, uint32_t shift, uint32
     const T c = beta * (P / acc - T(1)) / amax;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-        if (lane + 64 * k < n) img[id[k]] = fv[k] * (T(1) + c * av[k]);
+        if (lane + 64 * k < n) img[id[k]] = fv[k] * fmadd(c, av[k], T(1));
     }
 }
 
@@ -74,12 +83,13 @@ template <class T, class TC, class Img>
 __device__ void row_streamed(Img img, uint32_t shift, uint32_t wtot, T beta, const uint32_t *ids,
                              const TC *a, int n, T P, int lane)
 {
+#pragma clang fp contract(off)
     T acc = T(0), amax = T(0);
     for (int j = lane; j < n; j += 64) {
         uint32_t t = ids[j] + shift;
         t = t >= wtot ? t - wtot : t;
         T av = (T)a[j];
-        acc += av * img[t];
+        acc = fmadd(av, img[t], acc);
         amax = av > amax ? av : amax;
     }
     acc = wave_sum(acc);
@@ -89,7 +99,7 @@ __device__ void row_streamed(Img img, uint32_t shift, uint32_t wtot, T beta, con
     for (int j = lane; j < n; j += 64) {
         uint32_t t = ids[j] + shift;
         t = t >= wtot ? t - wtot : t;
-        img[t] = img[t] * (T(1) + c * (T)a[j]);
+        img[t] = img[t] * fmadd(c, (T)a[j], T(1));
     }
 }
 
