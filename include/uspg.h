@@ -57,7 +57,11 @@ enum {
     USPG_FAN_2D = 1,      /* point source (-D_so, 0), flat detector at x = D_sd - D_so      */
     USPG_CONE_3D = 2      /* point source (-D_so, 0, 0), flat U x V detector at x = D_sd - D_so */
 };
-enum { USPG_WEIGHTS_LENGTH = 0, USPG_WEIGHTS_BINARY = 1 };
+enum {
+    USPG_WEIGHTS_LENGTH = 0,  /* intersection lengths, view-0 rows shifted per view         */
+    USPG_WEIGHTS_BINARY = 1,  /* 1 per traversed cell, view-0 rows shifted per view         */
+    USPG_WEIGHTS_SEGMENTS = 2 /* the paper's literal scheme: binary, re-binned per view     */
+};
 enum { USPG_F32 = 0, USPG_F64 = 1 };
 enum { USPG_REMAP_POINT = 0, USPG_REMAP_BIJECTION = 1 };
 
@@ -106,7 +110,16 @@ void uspg_free_grid(uspg_grid *g);
  * W = det_half_u (columns) or det_half_v (rows).  Parallel 2D uses only
  * det_u and det_half_u.  src_axis = D_so, src_det = D_sd.
  * weights: LENGTH stores the intersection length of ray and cell, BINARY
- * stores 1 for every traversed cell (Sec. III.B).
+ * stores 1 for every traversed cell (Sec. III.B).  SEGMENTS is the paper's
+ * literal scheme (Sec. III.B-C, Alg. 1): each view-0 ray is cut only at the
+ * cylindrical and axial planes, and each piece is stored as (slice, ring,
+ * azimuth at both ends); for view v both azimuths advance by v span /
+ * n_views and every sector between them (eqs. 10-16) gets coefficient 1
+ * (a cell met by both passes of a line through one ring counts once).  With
+ * SEGMENTS any n_views and span are accepted (no USPG_E_SHIFT), the rows of
+ * every view are rebuilt on the fly during MART, the colouring is the union
+ * of every view's conflicts, coeff_dtype is ignored (records are FP64), and
+ * the handle runs through mart_run only (batches and engines reject it).
  * coeff_dtype: storage of the coefficients (USPG_F32 or USPG_F64).
  * colour_u, colour_v: 0 = choose the smallest valid lattice; otherwise the
  * lattice is checked and USPG_E_ARG is returned if two rays of one class
@@ -132,21 +145,24 @@ int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *scan, void *stre
                       uspg_coeffs **out);
 
 /* Sizes of the reference rows and the chosen lattice (classes are
- * c = (w mod colour_v) * colour_u + (u mod colour_u)).  NULL skips. */
+ * c = (w mod colour_v) * colour_u + (u mod colour_u)).  With SEGMENTS,
+ * nnz_ref and max_row count segment records.  NULL skips. */
 int uspg_coeffs_info(const uspg_coeffs *c, int64_t *nnz_ref, int64_t *n_rays,
                      int32_t *colour_u, int32_t *colour_v, int32_t *max_row,
                      int64_t *device_bytes);
 
 /* Host copy of the row of ray `ray` in view `view` (cells in the paper's
- * numbering, rotated to that view; lengths as stored).  Synchronous; for
- * inspection and tests.  *n receives the row length; USPG_E_NOMEM if it
- * exceeds cap (nothing written). */
+ * numbering, rotated to that view; lengths as stored; with SEGMENTS the
+ * re-binned row, cells ascending, lengths 1).  Synchronous; for inspection
+ * and tests.  *n receives the row length; USPG_E_NOMEM if it exceeds cap
+ * (nothing written). */
 int uspg_coeffs_row(const uspg_coeffs *c, int32_t view, int64_t ray, int64_t *cells,
                     double *lengths, int32_t cap, int32_t *n);
 
 /* Host copy of the conflict-offset map used by the colouring:
  * mark[dw * det_u + du] = 1 when two view-0 rays whose detector indices
- * differ by (du, dw) share a cell.  mark has det_u * det_v bytes. */
+ * differ by (du, dw) share a cell (with SEGMENTS: in any view).  mark has
+ * det_u * det_v bytes. */
 int uspg_coeffs_conflicts(const uspg_coeffs *c, uint8_t *mark);
 
 void uspg_free_coeffs(uspg_coeffs *c);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libuspg.so")
 # enumerations (mirror include/uspg.h)
 SECTORS = {"paper": 0, "multiple": 1, "explicit": 2}
 GEOMETRY = {"parallel2d": 0, "fan2d": 1, "cone3d": 2}
-WEIGHTS = {"length": 0, "binary": 1}
+WEIGHTS = {"length": 0, "binary": 1, "segments": 2}
 DTYPE = {torch.float32: 0, torch.float64: 1}
 REMAP = {"point": 0, "bijection": 1}
 
@@ -178,18 +178,24 @@ class Coeffs:
 
     @classmethod
     def from_workload(cls, grid: Grid, w, coeff_dtype=torch.float32, colour=(0, 0), stream=None):
+        weights = "segments" if w.rebin else ("binary" if w.binary else "length")
         return cls(grid, w.geometry, w.n_views, w.span, w.det_u, w.det_v, w.det_half_u, w.det_half_v,
-                   w.src_axis, w.src_det, "binary" if w.binary else "length", coeff_dtype, colour, stream)
+                   w.src_axis, w.src_det, weights, coeff_dtype, colour, stream)
 
     def row(self, view: int, ray: int):
         import numpy as np
         cap = max(self.max_row, 1)
-        cells = np.zeros(cap, dtype=np.int64)
-        lens = np.zeros(cap)
-        n = C.c_int32()
-        _check(lib().uspg_coeffs_row(self.handle, view, ray, cells.ctypes.data_as(C.c_void_p),
-                                     lens.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
-        return cells[:n.value].copy(), lens[:n.value].copy()
+        while True:
+            cells = np.zeros(cap, dtype=np.int64)
+            lens = np.zeros(cap)
+            n = C.c_int32()
+            rc = lib().uspg_coeffs_row(self.handle, view, ray, cells.ctypes.data_as(C.c_void_p),
+                                       lens.ctypes.data_as(C.c_void_p), cap, C.byref(n))
+            if rc == -3 and n.value > cap:    # re-binned rows can outgrow max_row
+                cap = n.value
+                continue
+            _check(rc)
+            return cells[:n.value].copy(), lens[:n.value].copy()
 
     def conflicts(self):
         import numpy as np

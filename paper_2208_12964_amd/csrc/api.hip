@@ -180,9 +180,32 @@ int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *sc, void *stream
     if (cone && !(g->H > 0 && sc->det_half_v > 0)) return fail(USPG_E_ARG, "cone beam needs a cylinder and det_half_v > 0");
     if (sc->geometry != USPG_PARALLEL_2D && !(sc->src_axis > g->R && sc->src_det > 0))
         return fail(USPG_E_ARG, "the source must lie outside the cylinder");
-    if (sc->weights != USPG_WEIGHTS_LENGTH && sc->weights != USPG_WEIGHTS_BINARY) return fail(USPG_E_ARG, "weights");
+    if (sc->weights != USPG_WEIGHTS_LENGTH && sc->weights != USPG_WEIGHTS_BINARY &&
+        sc->weights != USPG_WEIGHTS_SEGMENTS)
+        return fail(USPG_E_ARG, "weights");
     if (sc->coeff_dtype != USPG_F32 && sc->coeff_dtype != USPG_F64) return fail(USPG_E_ARG, "coeff_dtype");
     if ((int64_t)sc->det_u * sc->det_v >= (int64_t)1 << 31) return fail(USPG_E_ARG, "too many rays");
+    hipStream_t s = (hipStream_t)stream;
+    if (sc->weights == USPG_WEIGHTS_SEGMENTS) {
+        // the paper's literal scheme: any number of views, rows re-binned per view
+        if (g->nr >= (1 << 16) || g->nz >= (1 << 16)) return fail(USPG_E_ARG, "segment records need < 65536 rings and slices");
+        auto *c = new uspg_coeffs();
+        c->g = g;
+        c->scan = *sc;
+        c->device = g->device;
+        c->segments = true;
+        c->nrays = (int64_t)sc->det_u * sc->det_v;
+        if ((rc = segments_reference_view(c, s)) != USPG_OK || (rc = colour_segments(c, s)) != USPG_OK) {
+            uspg_free_coeffs(c);
+            return rc;
+        }
+        c->nnz = c->nseg;
+        c->max_row = c->max_seg;
+        c->device_bytes = (int64_t)(c->segptr.bytes + c->seg_sr.bytes + c->seg_pa.bytes + c->seg_pb.bytes +
+                                    c->seg_partner.bytes);
+        *out = c;
+        return USPG_OK;
+    }
     // view group: a view step must be a whole number of sectors in every ring
     double qf = sc->n_views * kTwoPi / sc->span;
     int q = (int)std::floor(qf + 0.5);
@@ -211,7 +234,6 @@ int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *sc, void *stream
     }
     c->nrays = (int64_t)sc->det_u * sc->det_v;
     const std::vector<int32_t> &ring_of = c->ring_of_off;
-    hipStream_t s = (hipStream_t)stream;
     if ((rc = c->d_kq.alloc(sizeof(int32_t) * g->nr)) != USPG_OK ||
         (rc = c->d_hq.alloc(sizeof(int32_t) * (g->nr + 1))) != USPG_OK ||
         (rc = c->d_ring_of_off.alloc(sizeof(int32_t) * c->Cq)) != USPG_OK) {
@@ -254,6 +276,19 @@ int uspg_coeffs_row(const uspg_coeffs *c, int32_t view, int64_t ray, int64_t *ce
     if (view < 0 || view >= c->scan.n_views || ray < 0 || ray >= c->nrays) return fail(USPG_E_ARG, "view or ray out of range");
     int rc = check_device(c->device);
     if (rc != USPG_OK) return rc;
+    if (c->segments) {
+        std::vector<int64_t> row;
+        if ((rc = segments_row(c, view, ray, row)) != USPG_OK) return rc;
+        *n = (int32_t)row.size();
+        if (*n > cap) return fail(USPG_E_NOMEM, "row longer than cap");
+        if (*n == 0) return USPG_OK;
+        if (!cells || !lengths) return fail(USPG_E_ARG, "null output");
+        for (int32_t j = 0; j < *n; ++j) {
+            cells[j] = row[j];
+            lengths[j] = 1.0;
+        }
+        return USPG_OK;
+    }
     int64_t rp[2];
     USPG_HIP(hipMemcpy(rp, c->rowptr.as<int64_t>() + ray, sizeof(rp), hipMemcpyDeviceToHost));
     int32_t len = (int32_t)(rp[1] - rp[0]);
@@ -298,6 +333,11 @@ void uspg_free_coeffs(uspg_coeffs *c)
     c->d_kq.release();
     c->d_hq.release();
     c->d_ring_of_off.release();
+    c->segptr.release();
+    c->seg_sr.release();
+    c->seg_pa.release();
+    c->seg_pb.release();
+    c->seg_partner.release();
     delete c;
 }
 
@@ -305,7 +345,7 @@ size_t uspg_mart_workspace_bytes(const uspg_coeffs *c, int32_t dtype, double tol
 {
     if (!c) return 0;
     size_t sz = dtype == USPG_F64 ? sizeof(double) : sizeof(float);
-    size_t n = (size_t)c->Wtot * sz;
+    size_t n = (size_t)(c->segments ? c->g->ncells : c->Wtot) * sz;
     return tol > 0 ? 2 * n + 16 : n;
 }
 

@@ -451,6 +451,7 @@ int uspg_build_batch(int32_t n, const uspg_coeffs *const *coeffs, int32_t dtype,
     for (int i = 0; i < n; ++i) {
         if (!coeffs[i]) return fail(USPG_E_ARG, "null coefficients in batch");
         if (coeffs[i]->device != dev) return fail(USPG_E_ARG, "coefficients on another device");
+        if (coeffs[i]->segments) return fail(USPG_E_ARG, "segment-record coefficients run through mart_run only");
         if (coeffs[i]->scan.coeff_dtype != coeffs[0]->scan.coeff_dtype)
             return fail(USPG_E_ARG, "all problems of a batch must share the coefficient type");
     }
@@ -615,6 +616,7 @@ int uspg_engine_admit(uspg_engine *e, const uspg_coeffs *c, const void *proj, vo
     if (!e || !c || !proj || !image || !work) return fail(USPG_E_ARG, "null argument");
     if (n_sweeps <= 0 || !(beta > 0)) return fail(USPG_E_ARG, "n_sweeps > 0 and beta > 0");
     if (c->scan.coeff_dtype != e->coeff_dtype) return fail(USPG_E_ARG, "coefficient type differs from the engine's");
+    if (c->segments) return fail(USPG_E_ARG, "segment-record coefficients run through mart_run only");
     if (work_bytes < uspg_mart_workspace_bytes(c, e->dtype, 0.0)) return fail(USPG_E_NOMEM, "work space too small");
     int rc = check_device(e->device);
     if (rc != USPG_OK) return rc;

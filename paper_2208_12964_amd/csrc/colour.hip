@@ -67,49 +67,42 @@ bool lattice_ok(const std::vector<uint8_t> &mark, int U, int V, int ku, int kv)
 
 }  // namespace
 
-int colour_reference_view(uspg_coeffs *c, hipStream_t s)
+int conflict_marks(const int64_t *rowptr, const uint32_t *ids, int64_t nrays, int64_t nnz, int64_t ncells,
+                   int U, uint8_t *mark, hipStream_t s)
 {
-    const int U = c->scan.det_u, V = c->scan.det_v;
-    const int64_t ncells = c->Wtot, nrays = c->nrays;   // ids live in the device layout
     uint32_t *cnt = nullptr, *cptr = nullptr, *rays = nullptr;
-    uint8_t *mark = nullptr;
     int rc = USPG_OK;
-    c->mark.assign((size_t)U * V, 0);
     do {
         if (hipMalloc((void **)&cnt, sizeof(uint32_t) * (ncells + 1)) != hipSuccess ||
             hipMalloc((void **)&cptr, sizeof(uint32_t) * (ncells + 1)) != hipSuccess ||
-            hipMalloc((void **)&rays, sizeof(uint32_t) * (c->nnz > 0 ? c->nnz : 1)) != hipSuccess ||
-            hipMalloc((void **)&mark, (size_t)U * V) != hipSuccess) {
+            hipMalloc((void **)&rays, sizeof(uint32_t) * (nnz > 0 ? nnz : 1)) != hipSuccess) {
             rc = fail(USPG_E_NOMEM, "colouring: device allocation failed");
             break;
         }
-        if (hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (ncells + 1), s) != hipSuccess ||
-            hipMemsetAsync(mark, 0, (size_t)U * V, s) != hipSuccess) {
+        if (hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (ncells + 1), s) != hipSuccess) {
             rc = fail(USPG_E_HIP, "colouring: memset failed");
             break;
         }
         const unsigned rb = (unsigned)((nrays * 64 + 255) / 256);
-        const int64_t *rp = c->rowptr.as<int64_t>();
-        const uint32_t *ids = c->ids.as<uint32_t>();
-        hipLaunchKernelGGL(count_cells, dim3(rb), dim3(256), 0, s, rp, ids, nrays, cnt);
+        hipLaunchKernelGGL(count_cells, dim3(rb), dim3(256), 0, s, rowptr, ids, nrays, cnt);
         if ((rc = exclusive_scan_u32(cnt, cptr, ncells, s)) != USPG_OK) break;
         if (hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (ncells + 1), s) != hipSuccess) {
             rc = fail(USPG_E_HIP, "colouring: memset failed");
             break;
         }
-        hipLaunchKernelGGL(fill_cells, dim3(rb), dim3(256), 0, s, rp, ids, nrays, cptr, cnt, rays);
+        hipLaunchKernelGGL(fill_cells, dim3(rb), dim3(256), 0, s, rowptr, ids, nrays, cptr, cnt, rays);
         hipLaunchKernelGGL(pair_offsets, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, s,
                            cptr, rays, ncells, U, mark);
         if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "colouring: launch failed"); break; }
-        if (hipMemcpyAsync(c->mark.data(), mark, (size_t)U * V, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            rc = fail(USPG_E_HIP, "colouring: copy failed");
-            break;
-        }
+        if (hipStreamSynchronize(s) != hipSuccess) { rc = fail(USPG_E_HIP, "colouring failed"); break; }
     } while (0);
-    (void)hipFree(cnt); (void)hipFree(cptr); (void)hipFree(rays); (void)hipFree(mark);
-    if (rc != USPG_OK) return rc;
+    (void)hipFree(cnt); (void)hipFree(cptr); (void)hipFree(rays);
+    return rc;
+}
 
+int choose_lattice(uspg_coeffs *c)
+{
+    const int U = c->scan.det_u, V = c->scan.det_v;
     if (c->scan.colour_u > 0 || c->scan.colour_v > 0) {
         int ku = c->scan.colour_u > 0 ? c->scan.colour_u : 1;
         int kv = c->scan.colour_v > 0 ? c->scan.colour_v : 1;
@@ -132,6 +125,24 @@ int colour_reference_view(uspg_coeffs *c, hipStream_t s)
         }
     }
     return fail(USPG_E_INTERNAL, "no valid colour lattice");
+}
+
+int colour_reference_view(uspg_coeffs *c, hipStream_t s)
+{
+    const int U = c->scan.det_u, V = c->scan.det_v;
+    uint8_t *mark = nullptr;
+    c->mark.assign((size_t)U * V, 0);
+    if (hipMalloc((void **)&mark, (size_t)U * V) != hipSuccess) return fail(USPG_E_NOMEM, "colouring: allocation");
+    int rc = USPG_OK;
+    if (hipMemsetAsync(mark, 0, (size_t)U * V, s) != hipSuccess) rc = fail(USPG_E_HIP, "colouring: memset failed");
+    // ids live in the device layout
+    if (rc == USPG_OK)
+        rc = conflict_marks(c->rowptr.as<int64_t>(), c->ids.as<uint32_t>(), c->nrays, c->nnz, c->Wtot, U, mark, s);
+    if (rc == USPG_OK && hipMemcpy(c->mark.data(), mark, (size_t)U * V, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(USPG_E_HIP, "colouring: copy failed");
+    (void)hipFree(mark);
+    if (rc != USPG_OK) return rc;
+    return choose_lattice(c);
 }
 
 }  // namespace uspg

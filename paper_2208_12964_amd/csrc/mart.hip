@@ -16,6 +16,7 @@
 #include <atomic>
 
 #include "mart_row.hpp"
+#include "segments.hpp"
 #include "uspg_internal.hpp"
 
 namespace uspg {
@@ -66,6 +67,80 @@ __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
     const uint32_t *ids = A.ids + beg;
     const TC *a = A.a + beg;
     mart_row<T, TC, MAXC>(A.f, A.shift, A.wtot, A.beta, ids, a, n, A.P[r], lane);
+}
+
+// The paper's literal variant: one (view, class) batch with each ray's row
+// rebuilt from its segment records (segments.hpp).  Lane j takes records j,
+// j + 64, ...; a record meets a run of sectors of one ring and slice, minus
+// those its partner record (the line's other pass through that ring and
+// slice) already met.  Binary coefficients: Pbar is the sum of f over the
+// row and every cell gets the same factor 1 + beta (P / Pbar - 1) (eq. 18
+// with a_j = a_max = 1).  The image is in the paper's numbering.
+template <class T>
+struct RebinMartArgs {
+    const int64_t *segptr;
+    const uint32_t *sr;
+    const double *pa, *pb;
+    const int32_t *partner;
+    const int32_t *ng;
+    const int64_t *head;
+    int64_t c2d;
+    const T *P;
+    T *f;
+    double theta;
+    int U, cu, cw, Ku, Kv, nu, ncls, nblk;
+    T beta;
+};
+
+template <class T, bool UPDATE>
+__device__ __forceinline__ T rebin_pass(const RebinMartArgs<T> &A, int64_t b, int n, int lane, T g, int *cells)
+{
+    T acc = T(0);
+    int m = 0;
+    for (int j = lane; j < n; j += 64) {
+        const uint32_t sr = A.sr[b + j];
+        const int ring = seg::ring_of(sr), ng = A.ng[ring];
+        int first, count, pf = 0, pc = 0;
+        seg::rebin_range(ng, A.pa[b + j], A.pb[b + j], A.theta, first, count);
+        const int32_t pj = A.partner[b + j];
+        if (pj >= 0) seg::rebin_range(ng, A.pa[b + pj], A.pb[b + pj], A.theta, pf, pc);
+        T *fr = A.f + (int64_t)seg::slice_of(sr) * A.c2d + A.head[ring];
+        for (int q = 0; q < count; ++q) {
+            int s = first + q;
+            if (s >= ng) s -= ng;
+            if (pc && seg::in_range(s, pf, pc, ng)) continue;
+            if (UPDATE) {
+                fr[s] = fr[s] * g;
+            } else {
+                acc += fr[s];
+                ++m;
+            }
+        }
+    }
+    if (cells) *cells = m;
+    return acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void mart_rebin(RebinMartArgs<T> A)
+{
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    const int x = xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6);
+    if (x >= A.ncls) return;
+    const int w = A.cw + (x / A.nu) * A.Kv;
+    const int u = A.cu + (x % A.nu) * A.Ku;
+    const int64_t r = (int64_t)w * A.U + u;
+    const int64_t b = A.segptr[r];
+    const int n = (int)(A.segptr[r + 1] - b);
+    if (n == 0) return;
+    int m = 0;
+    T acc = rebin_pass<T, false>(A, b, n, lane, T(0), &m);
+    acc = wave_sum(acc);
+    m = wave_sum(m);
+    if (m == 0 || !(acc > T(0))) return;
+    const T g = T(1) + A.beta * (A.P[r] / acc - T(1));
+    rebin_pass<T, true>(A, b, n, lane, g, nullptr);
 }
 
 // Layout maps between the paper's numbering and the wedge-major layout.
@@ -250,6 +325,87 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
     return USPG_OK;
 }
 
+template <class T>
+int run_segments(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_sweeps, double beta,
+                 double tol, int32_t *sweeps_done, hipStream_t s)
+{
+    const uspg_grid *g = c->g;
+    const uint32_t ncells = (uint32_t)g->ncells;
+    T *f = static_cast<T *>(work);
+    T *old = tol > 0 ? f + ncells : nullptr;
+    using UB = typename Bits<T>::U;
+    UB *mx = tol > 0 ? reinterpret_cast<UB *>(old + ncells) : nullptr;
+    USPG_HIP(hipMemcpyAsync(f, image, sizeof(T) * ncells, hipMemcpyDeviceToDevice, s));
+    RebinMartArgs<T> A{};
+    A.segptr = c->segptr.as<int64_t>();
+    A.sr = c->seg_sr.as<uint32_t>();
+    A.pa = c->seg_pa.as<double>();
+    A.pb = c->seg_pb.as<double>();
+    A.partner = c->seg_partner.as<int32_t>();
+    A.ng = g->d_ng.as<int32_t>();
+    A.head = g->d_head.as<int64_t>();
+    A.c2d = g->c2d;
+    A.f = f;
+    A.U = c->scan.det_u;
+    A.Ku = c->Ku; A.Kv = c->Kv;
+    A.beta = (T)beta;
+    const int K = c->Ku * c->Kv;
+    const unsigned pb = (ncells + 255) / 256;
+    int done = 0;
+    const bool timing = g_timing.load() != 0 && tol == 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int64_t launches = 0;
+    if (timing) {
+        USPG_HIP(hipEventCreate(&ev0));
+        USPG_HIP(hipEventCreate(&ev1));
+        USPG_HIP(hipEventRecord(ev0, s));
+    }
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        if (tol > 0) USPG_HIP(hipMemcpyAsync(old, f, sizeof(T) * ncells, hipMemcpyDeviceToDevice, s));
+        for (int v = 0; v < c->scan.n_views; ++v) {
+            A.P = proj + (int64_t)v * c->nrays;
+            A.theta = seg::view_angle(v, c->scan.span, c->scan.n_views);
+            for (int cl = 0; cl < K; ++cl) {
+                A.cu = cl % c->Ku;
+                A.cw = cl / c->Ku;
+                A.nu = (c->scan.det_u - A.cu + c->Ku - 1) / c->Ku;
+                const int nw = (c->scan.det_v - A.cw + c->Kv - 1) / c->Kv;
+                A.ncls = A.nu * nw;
+                A.nblk = (A.ncls + kWaves - 1) / kWaves;
+                if (A.ncls == 0) continue;
+                hipLaunchKernelGGL(mart_rebin<T>, dim3(A.nblk), dim3(kBlock), 0, s, A);
+                ++launches;
+            }
+        }
+        USPG_HIP(hipGetLastError());
+        ++done;
+        if (tol > 0) {
+            USPG_HIP(hipMemsetAsync(mx, 0, sizeof(UB), s));
+            unsigned nb = pb < 4096 ? pb : 4096;
+            hipLaunchKernelGGL(max_rel_change<T>, dim3(nb), dim3(256), 0, s, f, old, ncells, mx);
+            UB hb = 0;
+            USPG_HIP(hipMemcpyAsync(&hb, mx, sizeof(UB), hipMemcpyDeviceToHost, s));
+            USPG_HIP(hipStreamSynchronize(s));
+            T hv;
+            __builtin_memcpy(&hv, &hb, sizeof(hv));
+            if ((double)hv <= tol) break;
+        }
+    }
+    if (timing) {
+        USPG_HIP(hipEventRecord(ev1, s));
+        USPG_HIP(hipEventSynchronize(ev1));
+        float ms = 0.f;
+        USPG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        g_timing_ns += (int64_t)((double)ms * 1e6);
+        g_timing_launches += launches;
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
+    USPG_HIP(hipMemcpyAsync(image, f, sizeof(T) * ncells, hipMemcpyDeviceToDevice, s));
+    if (sweeps_done) *sweeps_done = done;
+    return USPG_OK;
+}
+
 }  // namespace
 
 int layout_permute(const uspg_coeffs *c, int dtype, const void *src, void *dst, int to_native_layout,
@@ -294,6 +450,11 @@ int mart_timing(int enable, double *batch_ms, int64_t *batch_launches)
 int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work,
                 int n_sweeps, double beta, double tol, int32_t *sweeps_done, hipStream_t s)
 {
+    if (c->segments) {
+        if (dtype == USPG_F32)
+            return run_segments<float>(c, (const float *)proj, (float *)image, work, n_sweeps, beta, tol, sweeps_done, s);
+        return run_segments<double>(c, (const double *)proj, (double *)image, work, n_sweeps, beta, tol, sweeps_done, s);
+    }
     const bool cf64 = c->scan.coeff_dtype == USPG_F64;
     if (dtype == USPG_F32) {
         if (cf64)

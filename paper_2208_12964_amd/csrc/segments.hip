@@ -1,0 +1,253 @@
+// Segment records of the reference view and their colouring (the paper's
+// literal scheme, Sec. III.B-C, Alg. 1; see segments.hpp).
+//
+// Build: one thread per view-0 ray counts its records, a scan places them,
+// a second pass writes (slice << 16 | ring, phi_a, phi_b) and, for a record
+// in the ring just outside the innermost ring the line reaches, the index of
+// the earlier record of the same ring and slice (the line's other pass
+// through that ring).  Those two can meet the same sectors, which must count
+// once; no other pair of records of a ray can (the grid's sector rule keeps
+// the passes through any outer ring more than a sector apart).
+//
+// Colouring: re-binning by a rotation that is not a whole number of sectors
+// changes which rays meet, so the conflict offsets are the union over every
+// view of the offsets of rays sharing a cell in that view (rows rebuilt per
+// view, then the same cell -> rays transpose as the reference colouring).
+#include <algorithm>
+
+#include "segments.hpp"
+#include "uspg_internal.hpp"
+
+namespace uspg {
+namespace {
+
+using walk::TraceGeo;
+
+using seg::CountSink;
+using seg::FillSink;
+
+__global__ __launch_bounds__(256) void seg_count(TraceGeo G, int64_t nrays, uint32_t *cnt)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrays) return;
+    CountSink sk;
+    cnt[r] = (uint32_t)seg::segments_of_ray(G, r, sk);
+}
+
+__global__ __launch_bounds__(256) void seg_fill(TraceGeo G, int64_t nrays, const int64_t *segptr, uint32_t *sr,
+                                                double *pa, double *pb, int32_t *partner)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrays) return;
+    FillSink sk{sr, pa, pb, partner, segptr[r]};
+    seg::segments_of_ray(G, r, sk);
+}
+
+__global__ void max_u32(const uint32_t *v, int64_t n, unsigned int *mx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(mx, v[i]);
+}
+
+// Rows of one view from the records: count pass (ids == nullptr) and fill.
+struct RebinArgs {
+    const int64_t *segptr;
+    const uint32_t *sr;
+    const double *pa, *pb;
+    const int32_t *partner;
+    const int32_t *ng;
+    const int64_t *head;
+    int64_t c2d, nrays;
+    double theta;
+};
+
+struct CountEmit {
+    __device__ void operator()(int64_t) {}
+};
+
+struct WriteEmit {
+    uint32_t *ids;
+    int64_t at;
+    __device__ void operator()(int64_t cell) { ids[at++] = (uint32_t)cell; }
+};
+
+__device__ inline int64_t rebin_ray(const RebinArgs &A, int64_t r, const int64_t *rowptr, uint32_t *ids)
+{
+    const int64_t b = A.segptr[r], n = A.segptr[r + 1] - b;
+    if (ids) {
+        WriteEmit e{ids, rowptr[r]};
+        return seg::rebin_cells(A.sr + b, A.pa + b, A.pb + b, A.partner + b, n, A.ng, A.head, A.c2d, A.theta, e);
+    }
+    CountEmit e;
+    return seg::rebin_cells(A.sr + b, A.pa + b, A.pb + b, A.partner + b, n, A.ng, A.head, A.c2d, A.theta, e);
+}
+
+__global__ __launch_bounds__(256) void rebin_count(RebinArgs A, uint32_t *cnt)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= A.nrays) return;
+    cnt[r] = (uint32_t)rebin_ray(A, r, nullptr, nullptr);
+}
+
+__global__ __launch_bounds__(256) void rebin_fill(RebinArgs A, const int64_t *rowptr, uint32_t *ids)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= A.nrays) return;
+    rebin_ray(A, r, rowptr, ids);
+}
+
+TraceGeo geometry_of(const uspg_coeffs *c)
+{
+    const uspg_grid *g = c->g;
+    const uspg_scan_desc &sc = c->scan;
+    TraceGeo G{};
+    G.nr = g->nr; G.nz = g->nz; G.is3d = sc.geometry == USPG_CONE_3D; G.geom = sc.geometry;
+    G.R = g->R; G.r = g->r; G.h = g->h; G.z0 = g->z0; G.H = g->H;
+    G.ng = g->d_ng.as<int32_t>();
+    G.head = g->d_head.as<int64_t>();
+    G.U = sc.det_u; G.V = sc.det_v;
+    G.Wu = sc.det_half_u; G.Wv = sc.det_half_v; G.Dso = sc.src_axis; G.Dsd = sc.src_det;
+    G.eps = 1e-12 * g->R;
+    return G;
+}
+
+RebinArgs rebin_args(const uspg_coeffs *c, int view)
+{
+    RebinArgs A{};
+    A.segptr = c->segptr.as<int64_t>();
+    A.sr = c->seg_sr.as<uint32_t>();
+    A.pa = c->seg_pa.as<double>();
+    A.pb = c->seg_pb.as<double>();
+    A.partner = c->seg_partner.as<int32_t>();
+    A.ng = c->g->d_ng.as<int32_t>();
+    A.head = c->g->d_head.as<int64_t>();
+    A.c2d = c->g->c2d;
+    A.nrays = c->nrays;
+    A.theta = seg::view_angle(view, c->scan.span, c->scan.n_views);
+    return A;
+}
+
+}  // namespace
+
+int segments_reference_view(uspg_coeffs *c, hipStream_t s)
+{
+    const TraceGeo G = geometry_of(c);
+    const int64_t nrays = c->nrays;
+    const unsigned blocks = (unsigned)((nrays + 255) / 256);
+    uint32_t *cnt = nullptr;
+    unsigned int *mx = nullptr;
+    USPG_HIP(hipMalloc((void **)&cnt, sizeof(uint32_t) * (nrays + 1)));
+    if (hipMalloc((void **)&mx, sizeof(unsigned int)) != hipSuccess) {
+        (void)hipFree(cnt);
+        return fail(USPG_E_NOMEM, "segments: allocation failed");
+    }
+    int rc = USPG_OK;
+    do {
+        hipLaunchKernelGGL(seg_count, dim3(blocks), dim3(256), 0, s, G, nrays, cnt);
+        if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "seg_count launch failed"); break; }
+        if ((rc = c->segptr.alloc(sizeof(int64_t) * (nrays + 1))) != USPG_OK) break;
+        if ((rc = exclusive_scan_u32_to_i64(cnt, c->segptr.as<int64_t>(), nrays, s)) != USPG_OK) break;
+        if (hipMemsetAsync(mx, 0, sizeof(unsigned int), s) != hipSuccess) { rc = fail(USPG_E_HIP, "memset"); break; }
+        hipLaunchKernelGGL(max_u32, dim3(blocks), dim3(256), 0, s, cnt, nrays, mx);
+        int64_t ns = 0;
+        unsigned int mseg = 0;
+        if (hipMemcpyAsync(&ns, c->segptr.as<int64_t>() + nrays, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&mseg, mx, sizeof(unsigned int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = fail(USPG_E_HIP, "segments: reading the record count failed");
+            break;
+        }
+        c->nseg = ns;
+        c->max_seg = (int32_t)mseg;
+        const int64_t n1 = ns > 0 ? ns : 1;
+        if ((rc = c->seg_sr.alloc(sizeof(uint32_t) * n1)) != USPG_OK) break;
+        if ((rc = c->seg_pa.alloc(sizeof(double) * n1)) != USPG_OK) break;
+        if ((rc = c->seg_pb.alloc(sizeof(double) * n1)) != USPG_OK) break;
+        if ((rc = c->seg_partner.alloc(sizeof(int32_t) * n1)) != USPG_OK) break;
+        hipLaunchKernelGGL(seg_fill, dim3(blocks), dim3(256), 0, s, G, nrays, c->segptr.as<int64_t>(),
+                           c->seg_sr.as<uint32_t>(), c->seg_pa.as<double>(), c->seg_pb.as<double>(),
+                           c->seg_partner.as<int32_t>());
+        if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "seg_fill launch failed"); break; }
+        if (hipStreamSynchronize(s) != hipSuccess) { rc = fail(USPG_E_HIP, "seg_fill failed"); break; }
+    } while (0);
+    (void)hipFree(cnt);
+    (void)hipFree(mx);
+    return rc;
+}
+
+int colour_segments(uspg_coeffs *c, hipStream_t s)
+{
+    const int U = c->scan.det_u, V = c->scan.det_v;
+    const int64_t nrays = c->nrays;
+    const unsigned blocks = (unsigned)((nrays + 255) / 256);
+    c->mark.assign((size_t)U * V, 0);
+    uint32_t *cnt = nullptr, *ids = nullptr;
+    int64_t *rowptr = nullptr;
+    uint8_t *mark = nullptr;
+    int64_t cap = 0;
+    int rc = USPG_OK;
+    do {
+        if (hipMalloc((void **)&cnt, sizeof(uint32_t) * (nrays + 1)) != hipSuccess ||
+            hipMalloc((void **)&rowptr, sizeof(int64_t) * (nrays + 1)) != hipSuccess ||
+            hipMalloc((void **)&mark, (size_t)U * V) != hipSuccess) {
+            rc = fail(USPG_E_NOMEM, "segment colouring: allocation failed");
+            break;
+        }
+        if (hipMemsetAsync(mark, 0, (size_t)U * V, s) != hipSuccess) { rc = fail(USPG_E_HIP, "memset"); break; }
+        for (int v = 0; v < c->scan.n_views && rc == USPG_OK; ++v) {
+            const RebinArgs A = rebin_args(c, v);
+            hipLaunchKernelGGL(rebin_count, dim3(blocks), dim3(256), 0, s, A, cnt);
+            if ((rc = exclusive_scan_u32_to_i64(cnt, rowptr, nrays, s)) != USPG_OK) break;
+            int64_t nnz = 0;
+            if (hipMemcpyAsync(&nnz, rowptr + nrays, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                rc = fail(USPG_E_HIP, "segment colouring: reading the row count failed");
+                break;
+            }
+            if (nnz > cap) {
+                (void)hipFree(ids);
+                ids = nullptr;
+                cap = std::max<int64_t>(nnz, 1);
+                if (hipMalloc((void **)&ids, sizeof(uint32_t) * cap) != hipSuccess) {
+                    rc = fail(USPG_E_NOMEM, "segment colouring: allocation failed");
+                    break;
+                }
+            }
+            hipLaunchKernelGGL(rebin_fill, dim3(blocks), dim3(256), 0, s, A, rowptr, ids);
+            if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "rebin launch failed"); break; }
+            rc = conflict_marks(rowptr, ids, nrays, nnz, c->g->ncells, U, mark, s);
+        }
+        if (rc != USPG_OK) break;
+        if (hipMemcpy(c->mark.data(), mark, (size_t)U * V, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = fail(USPG_E_HIP, "segment colouring: copy failed");
+    } while (0);
+    (void)hipFree(cnt); (void)hipFree(ids); (void)hipFree(rowptr); (void)hipFree(mark);
+    if (rc != USPG_OK) return rc;
+    return choose_lattice(c);
+}
+
+int segments_row(const uspg_coeffs *c, int view, int64_t ray, std::vector<int64_t> &cells)
+{
+    int64_t sp[2];
+    USPG_HIP(hipMemcpy(sp, c->segptr.as<int64_t>() + ray, sizeof(sp), hipMemcpyDeviceToHost));
+    const int64_t n = sp[1] - sp[0];
+    cells.clear();
+    if (n == 0) return USPG_OK;
+    std::vector<uint32_t> sr(n);
+    std::vector<double> pa(n), pb(n);
+    std::vector<int32_t> partner(n);
+    USPG_HIP(hipMemcpy(sr.data(), c->seg_sr.as<uint32_t>() + sp[0], sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+    USPG_HIP(hipMemcpy(pa.data(), c->seg_pa.as<double>() + sp[0], sizeof(double) * n, hipMemcpyDeviceToHost));
+    USPG_HIP(hipMemcpy(pb.data(), c->seg_pb.as<double>() + sp[0], sizeof(double) * n, hipMemcpyDeviceToHost));
+    USPG_HIP(hipMemcpy(partner.data(), c->seg_partner.as<int32_t>() + sp[0], sizeof(int32_t) * n,
+                       hipMemcpyDeviceToHost));
+    const uspg_grid *g = c->g;
+    const double theta = seg::view_angle(view, c->scan.span, c->scan.n_views);
+    auto emit = [&cells](int64_t cell) { cells.push_back(cell); };
+    seg::rebin_cells(sr.data(), pa.data(), pb.data(), partner.data(), n, g->ng.data(), g->head.data(), g->c2d,
+                     theta, emit);
+    std::sort(cells.begin(), cells.end());
+    return USPG_OK;
+}
+
+}  // namespace uspg

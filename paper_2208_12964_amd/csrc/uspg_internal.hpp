@@ -74,6 +74,16 @@ struct uspg_coeffs {
     uspg::DevBuf d_kq, d_hq;      // int32 [nr]
     uspg::DevBuf d_ring_of_off;   // int32 [Cq]: ring of each within-slice offset, -1 padding
     int64_t device_bytes = 0;
+    // Segment-record mode (weights == USPG_WEIGHTS_SEGMENTS): the rows of a
+    // view are rebuilt from these records; the image stays in the paper's
+    // numbering and rowptr / ids / a and the wedge tables are unused.
+    bool segments = false;
+    int64_t nseg = 0;             // records
+    int32_t max_seg = 0;          // records of the longest ray
+    uspg::DevBuf segptr;          // int64 [nrays + 1]
+    uspg::DevBuf seg_sr;          // uint32 [nseg]: slice << 16 | ring
+    uspg::DevBuf seg_pa, seg_pb;  // double [nseg]: reference azimuths of the two ends
+    uspg::DevBuf seg_partner;     // int32 [nseg]: earlier record of the ray in the same ring and slice, -1
 };
 
 namespace uspg {
@@ -85,6 +95,16 @@ constexpr int kRingGroup = 4;
 int trace_reference_view(uspg_coeffs *c, hipStream_t s);
 // colour.hip
 int colour_reference_view(uspg_coeffs *c, hipStream_t s);
+// ORs into mark (device, det_u * det_v bytes) the offsets of every pair of
+// rays of the CSR (ids < ncells) that share a cell; synchronises s.
+int conflict_marks(const int64_t *rowptr, const uint32_t *ids, int64_t nrays, int64_t nnz, int64_t ncells,
+                   int U, uint8_t *mark, hipStream_t s);
+// Smallest valid lattice for c->mark (or the requested one).
+int choose_lattice(uspg_coeffs *c);
+// segments.hip
+int segments_reference_view(uspg_coeffs *c, hipStream_t s);
+int colour_segments(uspg_coeffs *c, hipStream_t s);
+int segments_row(const uspg_coeffs *c, int view, int64_t ray, std::vector<int64_t> &cells);
 // scan.hip
 int exclusive_scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, hipStream_t s);
 int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s);

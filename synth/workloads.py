@@ -44,6 +44,7 @@ class Workload:
     src_axis: float = 0.0
     src_det: float = 0.0
     binary: bool = False
+    rebin: bool = False           # the paper's literal scheme: segment records re-binned per view
     phantom: str = "ellipses"     # "ellipses" | "ellipsoids" | "body_inclusions" | "none"
     n_objects: int = 6
     seed: int = 1
