@@ -58,9 +58,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cone-256r-32v-hc")
-    ap.add_argument("--mode", default="single", choices=["single", "batch2d", "serve"],
+    ap.add_argument("--mode", default="single", choices=["single", "batch2d", "serve", "paper"],
                     help="single: the 256-ring cone path (default); batch2d: 64 mixed 2D slices "
-                         "one at a time vs one persistent launch; serve: the request loop")
+                         "one at a time vs one persistent launch; serve: the request loop; paper: the "
+                         "paper's Table 1 scans with its literal segment scheme and image quality")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=20, help="detector rows in the oracle sample")
     ap.add_argument("--sweeps", type=int, default=0, help="override the sweep count (profiling runs)")
@@ -257,8 +258,88 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_paper(args):
+    """The paper's own scans (Table 1: fan beam 256^2 / 512^2 / 1024^2 with
+    50 views, cone beam 128^3 with 70 views) with its literal scheme:
+    segment records re-binned per view, binary MART, bijection remap, and
+    MAE / RMSE / SSIM against the phantom on the Cartesian grid.
+    value = ray-cell updates/s of the 128^3 cone-beam solve."""
+    import torch
+
+    import paper_2208_12964_amd as U
+    import synth
+    from paper_2208_12964_amd.quality import report
+
+    dev = torch.device("cuda:0")
+    say = lambda m: print(m, file=sys.stderr, flush=True)   # noqa: E731
+    out_cfg = []
+    head = None
+    for name in ("paper-fan-256-50v", "paper-fan-512-50v", "paper-fan-1024-50v", "paper-cone-128-70v"):
+        w = synth.get(name)
+        if args.sweeps:
+            w = w.with_(sweeps=args.sweeps)
+        P = synth.make_projections_torch(w, dev, torch.float32).reshape(-1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = U.Grid.from_workload(w)
+        co = U.Coeffs.from_workload(g, w)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        work = torch.empty(co.workspace_bytes(), dtype=torch.uint8, device=dev)
+        warm = torch.ones(g.n_cells, device=dev)
+        U.mart(co, P, warm, 1, w.beta, work=work)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(max(1, args.steps)):
+            img = torch.ones(g.n_cells, device=dev)
+            U.mart_timing(True)
+            t0 = time.perf_counter()
+            U.mart(co, P, img, w.sweeps, w.beta, work=work)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            ms, launches = U.mart_timing(False)
+            best = el if best is None or el < best else best
+        cart_b = U.to_cartesian(g, img, 2 * w.n_rings, mode="bijection")   # the paper's display map
+        cart = U.to_cartesian(g, img, 2 * w.n_rings)                       # geometric: for the figures
+        torch.cuda.synchronize()
+        q = report(w, cart)
+        q_b = report(w, cart_b)
+        upd = int(co.view_nnz().sum()) * w.sweeps
+        rec = {"workload": name, "rings": w.n_rings, "slices": w.n_slices, "views": w.n_views,
+               "detector": f"{w.det_u}x{w.det_v}", "sweeps": w.sweeps, "beta": w.beta,
+               "segments": co.nnz, "lattice": list(co.lattice), "updates_per_sweep": upd // w.sweeps,
+               "build_ms": build_s * 1e3, "mart_ms": best * 1e3, "avg_launch_us": ms * 1e3 / max(1, launches),
+               "launches": launches, "updates_per_s": upd / best, "quality_vs_phantom": q,
+               "quality_bijection_map": q_b}
+        say(f"paper: {json.dumps(rec)}")
+        out_cfg.append(rec)
+        head = rec
+    out = {"metric": "MART ray-cell updates/s, paper's 128^3 cone-beam scan (70 views, literal scheme)",
+           "value": head["updates_per_s"], "unit": "updates/s", "n_gpus": 1, "steps": max(1, args.steps),
+           "warmup": 1, "ms_per_step": head["mart_ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": head["workload"], "views": head["views"], "sweeps": head["sweeps"]},
+           "configs": out_cfg}
+    if not args.no_cpu_baseline:
+        from oracle import Oracle
+        w = synth.get("paper-cone-128-70v")
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        o = Oracle(w, nthreads=threads)
+        Pn = synth.make_projections_torch(w, "cpu").numpy()
+        seg = o.segments_view()
+        lat = o.colour_rebin(seg)
+        t0 = time.perf_counter()
+        o.mart_rebin(seg, lat, Pn, np.ones(o.n_cells), 2, w.beta)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 2 * head["updates_per_sweep"] / el, "unit": "updates/s", "cores": threads,
+                               "kind": "oracle", "sample": f"2 MART sweeps of {w.name} (FP64, rows re-binned per view)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.mode == "paper" and args.gpus == 1:
+        return bench_paper(args)
     if args.mode == "batch2d" and args.gpus == 1:
         return bench_batch2d(args)
     if args.mode == "serve" and args.gpus == 1:

@@ -120,6 +120,12 @@ void uspg_free_grid(uspg_grid *g);
  * every view are rebuilt on the fly during MART, the colouring is the union
  * of every view's conflicts, coeff_dtype is ignored (records are FP64), and
  * the handle runs through mart_run only (batches and engines reject it).
+ * quarter (SEGMENTS only, else ignored): 1 traces only the rays with
+ * u < ceil(det_u / 2) and w < ceil(det_v / 2) and mirrors their records to
+ * the other rays (y -> -y maps azimuth phi to 2 pi - phi, z -> -z maps slice
+ * k to n_slices - 1 - k; Sec. III.C); 0 traces every ray.  The two agree
+ * except for segment ends exactly on a radial plane, where a mirrored
+ * azimuth can round to the other side.
  * coeff_dtype: storage of the coefficients (USPG_F32 or USPG_F64).
  * colour_u, colour_v: 0 = choose the smallest valid lattice; otherwise the
  * lattice is checked and USPG_E_ARG is returned if two rays of one class
@@ -134,6 +140,7 @@ typedef struct {
     int32_t weights;
     int32_t coeff_dtype;
     int32_t colour_u, colour_v;
+    int32_t quarter;        /* SEGMENTS only: 1 traces one detector quadrant and mirrors it */
 } uspg_scan_desc;
 
 /* Traces every view-0 ray through the grid on the device (FP64 geometry),
@@ -158,6 +165,11 @@ int uspg_coeffs_info(const uspg_coeffs *c, int64_t *nnz_ref, int64_t *n_rays,
  * (nothing written). */
 int uspg_coeffs_row(const uspg_coeffs *c, int32_t view, int64_t ray, int64_t *cells,
                     double *lengths, int32_t cap, int32_t *n);
+
+/* Entries of every view's rows (host, n_views entries): nnz_ref for every
+ * view with LENGTH / BINARY; with SEGMENTS the re-binned cells of that view
+ * (the MART work per view).  Synchronous. */
+int uspg_coeffs_view_nnz(const uspg_coeffs *c, int64_t *nnz_per_view);
 
 /* Host copy of the conflict-offset map used by the colouring:
  * mark[dw * det_u + du] = 1 when two view-0 rays whose detector indices

@@ -42,7 +42,7 @@ class _ScanDesc(C.Structure):
                 ("det_u", C.c_int32), ("det_v", C.c_int32), ("det_half_u", C.c_double),
                 ("det_half_v", C.c_double), ("src_axis", C.c_double), ("src_det", C.c_double),
                 ("weights", C.c_int32), ("coeff_dtype", C.c_int32), ("colour_u", C.c_int32),
-                ("colour_v", C.c_int32)]
+                ("colour_v", C.c_int32), ("quarter", C.c_int32)]
 
 
 _lib = None
@@ -66,6 +66,7 @@ def lib():
     L.uspg_coeffs_info.argtypes = [P, P, P, P, P, P, P]
     L.uspg_coeffs_row.argtypes = [P, I32, I64, P, P, I32, P]
     L.uspg_coeffs_conflicts.argtypes = [P, P]
+    L.uspg_coeffs_view_nnz.argtypes = [P, P]
     L.uspg_free_coeffs.argtypes = [P]
     L.uspg_free_coeffs.restype = None
     L.uspg_mart_workspace_bytes.argtypes = [P, I32, D]
@@ -88,7 +89,7 @@ def lib():
     L.uspg_engine_destroy.restype = None
     L.uspg_last_error.restype = C.c_char_p
     for name in ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_build_coeffs",
-                 "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "mart_run",
+                 "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "uspg_coeffs_view_nnz", "mart_run",
                  "uspg_to_cartesian", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
                  "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_engine_create",
                  "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info"):
@@ -159,11 +160,12 @@ class Coeffs:
     def __init__(self, grid: Grid, geometry: str, n_views: int, span: float, det_u: int, det_v: int = 1,
                  det_half_u: float = 1.0, det_half_v: float = 0.0, src_axis: float = 0.0,
                  src_det: float = 0.0, weights: str = "length", coeff_dtype=torch.float32,
-                 colour=(0, 0), stream=None):
+                 colour=(0, 0), stream=None, quarter: bool = False):
         L = lib()
         self.grid = grid
         d = _ScanDesc(GEOMETRY[geometry], n_views, span, det_u, det_v, det_half_u, det_half_v,
-                      src_axis, src_det, WEIGHTS[weights], DTYPE[coeff_dtype], colour[0], colour[1])
+                      src_axis, src_det, WEIGHTS[weights], DTYPE[coeff_dtype], colour[0], colour[1],
+                      1 if quarter else 0)
         h = C.c_void_p()
         _check(L.uspg_build_coeffs(grid.handle, C.byref(d), C.c_void_p(_stream(stream)), C.byref(h)))
         self.handle = h
@@ -180,7 +182,7 @@ class Coeffs:
     def from_workload(cls, grid: Grid, w, coeff_dtype=torch.float32, colour=(0, 0), stream=None):
         weights = "segments" if w.rebin else ("binary" if w.binary else "length")
         return cls(grid, w.geometry, w.n_views, w.span, w.det_u, w.det_v, w.det_half_u, w.det_half_v,
-                   w.src_axis, w.src_det, weights, coeff_dtype, colour, stream)
+                   w.src_axis, w.src_det, weights, coeff_dtype, colour, stream, quarter=w.quarter)
 
     def row(self, view: int, ray: int):
         import numpy as np
@@ -196,6 +198,13 @@ class Coeffs:
                 continue
             _check(rc)
             return cells[:n.value].copy(), lens[:n.value].copy()
+
+    def view_nnz(self):
+        """Row entries of every view (the MART work per view)."""
+        import numpy as np
+        out = np.zeros(self.n_views, dtype=np.int64)
+        _check(lib().uspg_coeffs_view_nnz(self.handle, out.ctypes.data_as(C.c_void_p)))
+        return out
 
     def conflicts(self):
         import numpy as np
@@ -396,7 +405,7 @@ class Engine:
 
 EXPORTED = ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_free_grid",
             "uspg_build_coeffs", "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts",
-            "uspg_free_coeffs", "uspg_mart_workspace_bytes", "mart_run", "uspg_to_cartesian",
+            "uspg_free_coeffs", "uspg_mart_workspace_bytes", "mart_run", "uspg_to_cartesian", "uspg_coeffs_view_nnz",
             "uspg_last_error", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
             "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_free_batch",
             "uspg_engine_create", "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info",

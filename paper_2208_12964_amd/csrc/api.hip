@@ -317,6 +317,14 @@ int uspg_coeffs_row(const uspg_coeffs *c, int32_t view, int64_t ray, int64_t *ce
     return USPG_OK;
 }
 
+int uspg_coeffs_view_nnz(const uspg_coeffs *c, int64_t *nnz_per_view)
+{
+    if (!c || !nnz_per_view) return fail(USPG_E_ARG, "null argument");
+    for (int v = 0; v < c->scan.n_views; ++v)
+        nnz_per_view[v] = c->segments ? c->view_nnz[v] : c->nnz;
+    return USPG_OK;
+}
+
 int uspg_coeffs_conflicts(const uspg_coeffs *c, uint8_t *mark)
 {
     if (!c || !mark) return fail(USPG_E_ARG, "null argument");

@@ -43,6 +43,65 @@ __global__ __launch_bounds__(256) void seg_fill(TraceGeo G, int64_t nrays, const
     seg::segments_of_ray(G, r, sk);
 }
 
+// Quarter tracing (Sec. III.C): the reference view is symmetric under
+// y -> -y (detector column u <-> U-1-u: azimuth phi -> 2 pi - phi) and, in
+// 3D, under z -> -z (row w <-> V-1-w: slice k -> Nz-1-k).  Only the rays of
+// one quadrant (u < ceil(U/2), w < ceil(V/2)) are traced; their records are
+// copied to the mirror rays with those maps, in the same order along the
+// ray (a mirror keeps the distance from the source).
+__device__ inline int mirror_rays(int uq, int wq, int U, int V, int64_t *out)
+{
+    const int um = U - 1 - uq, wm = V - 1 - wq;
+    int n = 0;
+    out[n++] = (int64_t)wq * U + uq;
+    if (um != uq) out[n++] = (int64_t)wq * U + um;
+    if (wm != wq) {
+        out[n++] = (int64_t)wm * U + uq;
+        if (um != uq) out[n++] = (int64_t)wm * U + um;
+    }
+    return n;
+}
+
+__global__ __launch_bounds__(256) void seg_count_q(TraceGeo G, int uh, int vh, uint32_t *cnt)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)uh * vh) return;
+    const int uq = (int)(q % uh), wq = (int)(q / uh);
+    CountSink sk;
+    const uint32_t n = (uint32_t)seg::segments_of_ray(G, (int64_t)wq * G.U + uq, sk);
+    int64_t rays[4];
+    const int m = mirror_rays(uq, wq, G.U, G.V, rays);
+    for (int j = 0; j < m; ++j) cnt[rays[j]] = n;
+}
+
+__global__ __launch_bounds__(256) void seg_fill_q(TraceGeo G, int uh, int vh, const int64_t *segptr, uint32_t *sr,
+                                                  double *pa, double *pb, int32_t *partner)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)uh * vh) return;
+    const int uq = (int)(q % uh), wq = (int)(q / uh);
+    const int64_t r0 = (int64_t)wq * G.U + uq;
+    FillSink sk{sr, pa, pb, partner, segptr[r0]};
+    const int n = seg::segments_of_ray(G, r0, sk);
+    const int um = G.U - 1 - uq, wm = G.V - 1 - wq;
+    const int64_t b0 = segptr[r0];
+    for (int mir = 1; mir < 4; ++mir) {
+        const bool my = mir & 1, mz = mir & 2;
+        if ((my && um == uq) || (mz && wm == wq)) continue;
+        const int64_t r = (int64_t)(mz ? wm : wq) * G.U + (my ? um : uq);
+        const int64_t b = segptr[r];
+        for (int j = 0; j < n; ++j) {
+            uint32_t x = sr[b0 + j];
+            double a = pa[b0 + j], c = pb[b0 + j];
+            seg::mirror_record(my, mz, G.nz, x, a, c);
+            sr[b + j] = x;
+            pa[b + j] = a;
+            pb[b + j] = c;
+            partner[b + j] = partner[b0 + j];
+        }
+    }
+}
+
 __global__ void max_u32(const uint32_t *v, int64_t n, unsigned int *mx)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -143,7 +202,13 @@ int segments_reference_view(uspg_coeffs *c, hipStream_t s)
     }
     int rc = USPG_OK;
     do {
-        hipLaunchKernelGGL(seg_count, dim3(blocks), dim3(256), 0, s, G, nrays, cnt);
+        const bool quarter = c->scan.quarter != 0;
+        const int uh = (c->scan.det_u + 1) / 2, vh = (c->scan.det_v + 1) / 2;
+        const unsigned qblocks = (unsigned)(((int64_t)uh * vh + 255) / 256);
+        if (quarter)
+            hipLaunchKernelGGL(seg_count_q, dim3(qblocks), dim3(256), 0, s, G, uh, vh, cnt);
+        else
+            hipLaunchKernelGGL(seg_count, dim3(blocks), dim3(256), 0, s, G, nrays, cnt);
         if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "seg_count launch failed"); break; }
         if ((rc = c->segptr.alloc(sizeof(int64_t) * (nrays + 1))) != USPG_OK) break;
         if ((rc = exclusive_scan_u32_to_i64(cnt, c->segptr.as<int64_t>(), nrays, s)) != USPG_OK) break;
@@ -164,9 +229,14 @@ int segments_reference_view(uspg_coeffs *c, hipStream_t s)
         if ((rc = c->seg_pa.alloc(sizeof(double) * n1)) != USPG_OK) break;
         if ((rc = c->seg_pb.alloc(sizeof(double) * n1)) != USPG_OK) break;
         if ((rc = c->seg_partner.alloc(sizeof(int32_t) * n1)) != USPG_OK) break;
-        hipLaunchKernelGGL(seg_fill, dim3(blocks), dim3(256), 0, s, G, nrays, c->segptr.as<int64_t>(),
-                           c->seg_sr.as<uint32_t>(), c->seg_pa.as<double>(), c->seg_pb.as<double>(),
-                           c->seg_partner.as<int32_t>());
+        if (quarter)
+            hipLaunchKernelGGL(seg_fill_q, dim3(qblocks), dim3(256), 0, s, G, uh, vh, c->segptr.as<int64_t>(),
+                               c->seg_sr.as<uint32_t>(), c->seg_pa.as<double>(), c->seg_pb.as<double>(),
+                               c->seg_partner.as<int32_t>());
+        else
+            hipLaunchKernelGGL(seg_fill, dim3(blocks), dim3(256), 0, s, G, nrays, c->segptr.as<int64_t>(),
+                               c->seg_sr.as<uint32_t>(), c->seg_pa.as<double>(), c->seg_pb.as<double>(),
+                               c->seg_partner.as<int32_t>());
         if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "seg_fill launch failed"); break; }
         if (hipStreamSynchronize(s) != hipSuccess) { rc = fail(USPG_E_HIP, "seg_fill failed"); break; }
     } while (0);
@@ -181,6 +251,7 @@ int colour_segments(uspg_coeffs *c, hipStream_t s)
     const int64_t nrays = c->nrays;
     const unsigned blocks = (unsigned)((nrays + 255) / 256);
     c->mark.assign((size_t)U * V, 0);
+    c->view_nnz.clear();
     uint32_t *cnt = nullptr, *ids = nullptr;
     int64_t *rowptr = nullptr;
     uint8_t *mark = nullptr;
@@ -204,6 +275,7 @@ int colour_segments(uspg_coeffs *c, hipStream_t s)
                 rc = fail(USPG_E_HIP, "segment colouring: reading the row count failed");
                 break;
             }
+            c->view_nnz.push_back(nnz);
             if (nnz > cap) {
                 (void)hipFree(ids);
                 ids = nullptr;

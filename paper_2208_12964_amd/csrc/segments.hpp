@@ -182,6 +182,19 @@ USPG_HD inline bool in_range(int s, int first, int count, int ng)
     return d < count;
 }
 
+// Record of the mirror image of a view-0 ray (Sec. III.C): across y = 0
+// (detector column u <-> U-1-u) the azimuth phi becomes 2 pi - phi; across
+// z = 0 (row w <-> V-1-w) slice k becomes nz-1-k.  The order along the ray
+// and the partner indices are unchanged.
+USPG_HD inline void mirror_record(bool my, bool mz, int nz, uint32_t &sr, double &pa, double &pb)
+{
+    if (my) {
+        pa = pa > 0 ? kTwoPiS - pa : 0.0;
+        pb = pb > 0 ? kTwoPiS - pb : 0.0;
+    }
+    if (mz) sr = pack(nz - 1 - slice_of(sr), ring_of(sr));
+}
+
 // Segment sinks: count only, or write records with their partner (the
 // earlier record of the same ring and slice, searched only for the ring
 // just outside the innermost ring, jlo, back to the start of that ring's

@@ -84,6 +84,7 @@ struct uspg_coeffs {
     uspg::DevBuf seg_sr;          // uint32 [nseg]: slice << 16 | ring
     uspg::DevBuf seg_pa, seg_pb;  // double [nseg]: reference azimuths of the two ends
     uspg::DevBuf seg_partner;     // int32 [nseg]: earlier record of the ray in the same ring and slice, -1
+    std::vector<int64_t> view_nnz;  // re-binned entries of every view's rows
 };
 
 namespace uspg {

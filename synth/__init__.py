@@ -7,7 +7,7 @@ HIP library consume the arrays it writes, so it must not depend on either.
 """
 
 from .workloads import (  # noqa: F401
-    Workload, WORKLOADS, get, small_cone, cone, parallel, batch2d_members, serve_request,
+    Workload, WORKLOADS, get, small_cone, cone, parallel, batch2d_members, serve_request, paper_fan, paper_cone,
 )
 from .phantoms import (  # noqa: F401
     draw_phantom,
@@ -15,6 +15,7 @@ from .phantoms import (  # noqa: F401
     project,
     add_noise,
     make_projections,
+    phantom_value,
     make_projections_torch,
     scan_rays_torch,
 )

@@ -15,6 +15,9 @@ sees the same arrays:
   uniform in the body shrunk by 0.6; each sphere adds 5.0 - body value, so the
   inclusions read 5.0.
 
+The draws describe a unit disk (a cylinder of half-height 1); they are
+scaled by the workload's radius in x, y and by its half-height in z.
+
 Noise: P <- max(P + sigma * max(P) * N(0, 1), 0), drawn in array order.
 """
 
@@ -68,6 +71,13 @@ def draw_phantom(w: Workload) -> list:
             objs.append((cen, np.array([rad, rad, rad]), 0.0, 5.0 - mub))
     else:
         raise ValueError(f"unknown phantom {w.phantom!r}")
+    # the draws describe a unit disk / a cylinder of half-height 1: scale to
+    # the workload's radius and half-height (identity for R = 1, H = 2)
+    sr = w.radius
+    sz = w.height / 2 if w.height > 0 else 1.0
+    if sr != 1.0 or sz != 1.0:
+        scale = np.array([sr, sr, sz])
+        objs = [(cen * scale, ax * scale, ang, mu) for cen, ax, ang, mu in objs]
     return objs
 
 

@@ -45,6 +45,7 @@ class Workload:
     src_det: float = 0.0
     binary: bool = False
     rebin: bool = False           # the paper's literal scheme: segment records re-binned per view
+    quarter: bool = False         # literal scheme: trace one detector quadrant, mirror the rest
     phantom: str = "ellipses"     # "ellipses" | "ellipsoids" | "body_inclusions" | "none"
     n_objects: int = 6
     seed: int = 1
@@ -88,6 +89,42 @@ def parallel(name: str, n_rings: int, n_views: int, bins: int, m: int, **kw) -> 
         det_u=bins, det_v=1, det_half_u=1.0, **kw)
 
 
+def paper_fan(n_cart: int, n_views: int = 50, **kw) -> Workload:
+    """The paper's 2D phantom scans (Table 1): fan beam from (-8, 0) to a flat
+    detector centred at (8, 0), 101 detectors 0.05 apart, p views over a full
+    turn, relaxation 0.4, on the paper's grid with Nr = N / 2 rings for an
+    N x N Cartesian image, reconstructed with the literal segment scheme
+    (binary coefficients re-binned per view).  R = 1.2 keeps the disk inside
+    the fan (its edge rays reach +-2.43 of the +-2.525 detector)."""
+    nr = n_cart // 2
+    return Workload(
+        name=kw.pop("name", f"paper-fan-{n_cart}-{n_views}v"), geometry="fan2d", n_rings=nr, n_slices=1,
+        radius=kw.pop("radius", 1.2), height=0.0, sector_rule="paper", sector_multiple=1, n_views=n_views,
+        span=2 * math.pi, det_u=101, det_v=1, det_half_u=101 * 0.05 / 2, src_axis=8.0, src_det=16.0,
+        binary=True, rebin=True, quarter=kw.pop("quarter", True), phantom=kw.pop("phantom", "ellipses"),
+        n_objects=kw.pop("n_objects", 8),
+        seed=kw.pop("seed", 41), sweeps=kw.pop("sweeps", 20), beta=kw.pop("beta", 0.4),
+        remap_nc=n_cart, **kw)
+
+
+def paper_cone(n_cart: int, n_views: int = 70, **kw) -> Workload:
+    """The paper's 3D phantom scan (Table 1): cone beam from (-3, 0, 0) to a
+    flat detector centred at (10, 0, 0), 101 x 101 detectors 0.05 apart, p
+    views over a full turn, relaxation 0.4, on the paper's grid with N / 2
+    rings and N slices for an N^3 Cartesian volume, literal segment scheme.
+    R = 0.5, H = 1 keeps the cylinder inside the cone but for its rims next
+    to the source."""
+    nr = n_cart // 2
+    return Workload(
+        name=kw.pop("name", f"paper-cone-{n_cart}-{n_views}v"), geometry="cone3d", n_rings=nr, n_slices=n_cart,
+        radius=kw.pop("radius", 0.5), height=kw.pop("height", 1.0), sector_rule="paper", sector_multiple=1,
+        n_views=n_views, span=2 * math.pi, det_u=101, det_v=101, det_half_u=101 * 0.05 / 2,
+        det_half_v=101 * 0.05 / 2, src_axis=3.0, src_det=13.0, binary=True, rebin=True,
+        quarter=kw.pop("quarter", True),
+        phantom=kw.pop("phantom", "ellipsoids"), n_objects=kw.pop("n_objects", 10), seed=kw.pop("seed", 43),
+        sweeps=kw.pop("sweeps", 20), beta=kw.pop("beta", 0.4), remap_nc=n_cart, **kw)
+
+
 WORKLOADS = {
     # 2D parallel beam, FP64 plain MART: 32 rings, 8 views over 180 degrees, 64 bins.
     # Sector counts are multiples of 16 so that the 22.5-degree view step is a
@@ -103,6 +140,11 @@ WORKLOADS = {
     "cone-256r-32v-hc": cone("cone-256r-32v-hc", 256, 32, 512, 32, phantom="body_inclusions",
                              n_objects=4, seed=3, sweeps=20, beta=0.05, dtype="f32",
                              remap_nc=512),
+    # The paper's own scans (Table 1) with its literal coefficient scheme.
+    "paper-fan-256-50v": paper_fan(256),
+    "paper-fan-512-50v": paper_fan(512),
+    "paper-fan-1024-50v": paper_fan(1024),
+    "paper-cone-128-70v": paper_cone(128),
 }
 
 

@@ -62,6 +62,26 @@ int hs_segments(int64_t ray, int32_t *slice, int32_t *ring, double *pa, double *
     return n;
 }
 
+// Records of ray `ray` obtained as the library's quarter tracing does: the
+// quadrant ray's records mirrored (returns the count, or -3 if cap is small).
+int hs_segments_mirrored(int64_t ray, int32_t *slice, int32_t *ring, double *pa, double *pb, int32_t *partner,
+                         int cap)
+{
+    const int U = st.G.U, V = st.G.V;
+    const int u = (int)(ray % U), w = (int)(ray / U);
+    const int uq = u < U - 1 - u ? u : U - 1 - u, wq = w < V - 1 - w ? w : V - 1 - w;
+    const bool my = uq != u, mz = wq != w;
+    int n = hs_segments((int64_t)wq * U + uq, slice, ring, pa, pb, partner, cap);
+    if (n < 0) return n;
+    for (int j = 0; j < n; ++j) {
+        uint32_t sr = seg::pack(slice[j], ring[j]);
+        seg::mirror_record(my, mz, st.G.nz, sr, pa[j], pb[j]);
+        slice[j] = seg::slice_of(sr);
+        ring[j] = seg::ring_of(sr);
+    }
+    return n;
+}
+
 // Re-binned row (cells ascending) of one ray in one view.
 int hs_row(int view, int64_t ray, int64_t *cells, int cap)
 {

@@ -29,6 +29,7 @@ def hs():
                            C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int]
     L.hs_segments.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
     L.hs_row.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_int]
+    L.hs_segments_mirrored.argtypes = L.hs_segments.argtypes
     return L
 
 
@@ -44,10 +45,11 @@ class Lib:
         L.hs_setup(w.n_rings, w.n_slices, w.radius, w.height, P(ng), GEOM[w.geometry], int(w.is3d), w.det_u,
                    w.det_v, w.det_half_u, w.det_half_v, w.src_axis, w.src_det, w.span, w.n_views)
 
-    def segments(self, r, cap=8192):
+    def segments(self, r, cap=8192, mirrored=False):
         sl, rg, pr = (np.zeros(cap, dtype=np.int32) for _ in range(3))
         pa, pb = np.zeros(cap), np.zeros(cap)
-        n = self.L.hs_segments(r, P(sl), P(rg), P(pa), P(pb), P(pr), cap)
+        fn = self.L.hs_segments_mirrored if mirrored else self.L.hs_segments
+        n = fn(r, P(sl), P(rg), P(pa), P(pb), P(pr), cap)
         assert n >= 0
         return sl[:n], rg[:n], pa[:n], pb[:n], pr[:n]
 
@@ -90,3 +92,23 @@ def test_records_and_rows_equal_oracle(hs, w):
             assert np.array_equal(lib.row(v, r), rows.row(r)[0]), (v, r)
     if w.name == "sc-dip":
         assert partners > 0
+
+
+@pytest.mark.parametrize("w", cases()[:3] + [synth.paper_fan(64, 50), synth.paper_cone(24, 70)],
+                         ids=lambda w: w.name)
+def test_quarter_tracing_mirrors_records(hs, w):
+    """Sec. III.C: the records of the other three quadrants are the mirror
+    images of the traced quadrant's (same rings, mirrored slices, azimuths
+    2 pi - phi up to rounding), so the re-binned rows are the same."""
+    o = Oracle(w.with_(binary=True))
+    lib = Lib(hs, w, o)
+    for r in range(o.n_rays):
+        a = lib.segments(r)
+        b = lib.segments(r, mirrored=True)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[4], b[4]), r
+        d = np.abs(a[2] - b[2])
+        d = np.minimum(d, 2 * np.pi - d)           # 0 and 2 pi are one azimuth
+        assert d.max(initial=0) <= 1e-13, r
+        d = np.abs(a[3] - b[3])
+        d = np.minimum(d, 2 * np.pi - d)
+        assert d.max(initial=0) <= 1e-13, r
