@@ -367,7 +367,6 @@ struct uspg_engine {
     };
     std::vector<Slot> slots;
     std::vector<int> active;              // slot ids in launch order
-    bool dirty = true;
     int grid = 0;
     uspg::DevBuf d_static, d_dyn, d_wgbeg;
     void *h_stage = nullptr;              // pinned: static, dyn, wgbeg
@@ -405,7 +404,6 @@ int engine_upload(uspg_engine *e, hipStream_t s)
     USPG_HIP(hipMemcpyAsync(e->d_dyn.p, dyn, sizeof(ProblemDyn<T>) * n, hipMemcpyHostToDevice, s));
     USPG_HIP(hipMemcpyAsync(e->d_wgbeg.p, wg, sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
     USPG_HIP(hipEventRecord(e->staged, s));
-    e->dirty = false;
     return USPG_OK;
 }
 
@@ -637,7 +635,6 @@ int uspg_engine_admit(uspg_engine *e, const uspg_coeffs *c, const void *proj, vo
     sl.offset = e->gstep;
     sl.beta = beta;
     e->active.push_back(id);
-    e->dirty = true;
     if (slot) *slot = id;
     return USPG_OK;
 }
@@ -651,8 +648,8 @@ int uspg_engine_step(uspg_engine *e, int32_t n_steps, void *stream, int32_t *fin
     if (rc != USPG_OK) return rc;
     if (e->active.empty()) return USPG_OK;
     hipStream_t s = (hipStream_t)stream;
-    // step numbers inside a call start at 0: re-base the offsets every call
-    e->dirty = true;
+    // step numbers inside a call start at 0: the offsets are re-based and
+    // uploaded on every call
     rc = e->dtype == USPG_F64 ? engine_upload<double>(e, s) : engine_upload<float>(e, s);
     if (rc != USPG_OK) return rc;
     const bool cf64 = e->coeff_dtype == USPG_F64;

@@ -28,6 +28,26 @@ using row::wave_sum;
 
 constexpr int kWaves = 4;             // wavefronts per workgroup
 constexpr int kBlock = 64 * kWaves;
+// Grid cap of the batch kernel, in workgroups per compute unit: measured on
+// the 256-ring cone (43,690 rays per class), 16 per CU (4,096 on 256 CUs)
+// gave 122 us per batch against 135 us for one wavefront per ray; 8, 12,
+// 20, 24 and 32 per CU gave 128-150 us.  Classes of fewer rays are not
+// capped.
+constexpr int kBlocksPerCU = 16;
+
+int grid_cap()
+{
+    static int cap[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1 << 30;
+    if (!cap[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cap[dev] = kBlocksPerCU * cus;
+    }
+    return cap[dev];
+}
 
 template <class T, class TC>
 struct BatchArgs {
@@ -52,21 +72,23 @@ __device__ inline int xcd_block(int b, int nb)
     return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
+// The grid is capped (kBlocksPerCU workgroups per CU) and each wavefront
+// strides through the class by the grid's wavefront count; the rays of a
+// class share no cell, so the assignment changes no result.
 template <class T, class TC, int MAXC>
 __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
 {
     const int lane = threadIdx.x & 63;
-    const int x = xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6);
-    if (x >= A.ncls) return;
-    const int w = A.cw + (x / A.nu) * A.Kv;
-    const int u = A.cu + (x % A.nu) * A.Ku;
-    const int64_t r = (int64_t)w * A.U + u;
-    const int64_t beg = A.rowptr[r];
-    const int n = (int)(A.rowptr[r + 1] - beg);
-    if (n == 0) return;
-    const uint32_t *ids = A.ids + beg;
-    const TC *a = A.a + beg;
-    mart_row<T, TC, MAXC>(A.f, A.shift, A.wtot, A.beta, ids, a, n, A.P[r], lane);
+    const int total = A.nblk * kWaves;
+    for (int x = xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6); x < A.ncls; x += total) {
+        const int w = A.cw + (x / A.nu) * A.Kv;
+        const int u = A.cu + (x % A.nu) * A.Ku;
+        const int64_t r = (int64_t)w * A.U + u;
+        const int64_t beg = A.rowptr[r];
+        const int n = (int)(A.rowptr[r + 1] - beg);
+        if (n == 0) continue;
+        mart_row<T, TC, MAXC>(A.f, A.shift, A.wtot, A.beta, A.ids + beg, A.a + beg, n, A.P[r], lane);
+    }
 }
 
 // The paper's literal variant: one (view, class) batch with each ray's row
@@ -269,6 +291,7 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
     A.beta = (T)beta;
     const int nch = pick_nch(c->max_row);
     const int K = c->Ku * c->Kv;
+    const int cap = grid_cap();
     int done = 0;
     const bool timing = g_timing.load() != 0 && tol == 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -290,6 +313,7 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
                 const int nw = (c->scan.det_v - A.cw + c->Kv - 1) / c->Kv;
                 A.ncls = A.nu * nw;
                 A.nblk = (A.ncls + kWaves - 1) / kWaves;
+                if (A.nblk > cap) A.nblk = cap;
                 if (A.ncls == 0) continue;
                 launch_batch_n<T, TC>(nch, A, s);
                 ++launches;
