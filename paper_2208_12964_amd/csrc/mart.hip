@@ -114,34 +114,24 @@ struct RebinMartArgs {
     T beta;
 };
 
-template <class T, bool UPDATE>
-__device__ __forceinline__ T rebin_pass(const RebinMartArgs<T> &A, int64_t b, int n, int lane, T g, int *cells)
-{
-    T acc = T(0);
-    int m = 0;
-    for (int j = lane; j < n; j += 64) {
-        const uint32_t sr = A.sr[b + j];
-        const int ring = seg::ring_of(sr), ng = A.ng[ring];
-        int first, count, pf = 0, pc = 0;
-        seg::rebin_range(ng, A.pa[b + j], A.pb[b + j], A.theta, first, count);
-        const int32_t pj = A.partner[b + j];
-        if (pj >= 0) seg::rebin_range(ng, A.pa[b + pj], A.pb[b + pj], A.theta, pf, pc);
-        T *fr = A.f + (int64_t)seg::slice_of(sr) * A.c2d + A.head[ring];
-        for (int q = 0; q < count; ++q) {
-            int s = first + q;
-            if (s >= ng) s -= ng;
-            if (pc && seg::in_range(s, pf, pc, ng)) continue;
-            if (UPDATE) {
-                fr[s] = fr[s] * g;
-            } else {
-                acc += fr[s];
-                ++m;
-            }
-        }
+template <class T>
+struct SumEmit {
+    const T *f;
+    T acc;
+    int m;
+    __device__ void operator()(int64_t cell)
+    {
+        acc += f[cell];
+        ++m;
     }
-    if (cells) *cells = m;
-    return acc;
-}
+};
+
+template <class T>
+struct ScaleEmit {
+    T *f;
+    T g;
+    __device__ void operator()(int64_t cell) { f[cell] = f[cell] * g; }
+};
 
 template <class T>
 __global__ __launch_bounds__(kBlock) void mart_rebin(RebinMartArgs<T> A)
@@ -156,13 +146,15 @@ __global__ __launch_bounds__(kBlock) void mart_rebin(RebinMartArgs<T> A)
     const int64_t b = A.segptr[r];
     const int n = (int)(A.segptr[r + 1] - b);
     if (n == 0) return;
-    int m = 0;
-    T acc = rebin_pass<T, false>(A, b, n, lane, T(0), &m);
-    acc = wave_sum(acc);
-    m = wave_sum(m);
+    SumEmit<T> se{A.f, T(0), 0};
+    for (int j = lane; j < n; j += 64)
+        seg::rebin_record(A.sr + b, A.pa + b, A.pb + b, A.partner + b, j, A.ng, A.head, A.c2d, A.theta, se);
+    const T acc = wave_sum(se.acc);
+    const int m = wave_sum(se.m);
     if (m == 0 || !(acc > T(0))) return;
-    const T g = T(1) + A.beta * (A.P[r] / acc - T(1));
-    rebin_pass<T, true>(A, b, n, lane, g, nullptr);
+    ScaleEmit<T> ue{A.f, T(1) + A.beta * (A.P[r] / acc - T(1))};
+    for (int j = lane; j < n; j += 64)
+        seg::rebin_record(A.sr + b, A.pa + b, A.pb + b, A.partner + b, j, A.ng, A.head, A.c2d, A.theta, ue);
 }
 
 // Layout maps between the paper's numbering and the wedge-major layout.

@@ -130,29 +130,53 @@ struct WriteEmit {
     __device__ void operator()(int64_t cell) { ids[at++] = (uint32_t)cell; }
 };
 
-__device__ inline int64_t rebin_ray(const RebinArgs &A, int64_t r, const int64_t *rowptr, uint32_t *ids)
+__device__ inline int wave_sum_i(int v)
 {
-    const int64_t b = A.segptr[r], n = A.segptr[r + 1] - b;
-    if (ids) {
-        WriteEmit e{ids, rowptr[r]};
-        return seg::rebin_cells(A.sr + b, A.pa + b, A.pb + b, A.partner + b, n, A.ng, A.head, A.c2d, A.theta, e);
-    }
-    CountEmit e;
-    return seg::rebin_cells(A.sr + b, A.pa + b, A.pb + b, A.partner + b, n, A.ng, A.head, A.c2d, A.theta, e);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
+// One wavefront per ray: lane l takes records l, l + 64, ...
 __global__ __launch_bounds__(256) void rebin_count(RebinArgs A, uint32_t *cnt)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (r >= A.nrays) return;
-    cnt[r] = (uint32_t)rebin_ray(A, r, nullptr, nullptr);
+    const int64_t b = A.segptr[r], n = A.segptr[r + 1] - b;
+    int m = 0;
+    CountEmit e;
+    for (int64_t j = lane; j < n; j += 64)
+        m += seg::rebin_record(A.sr + b, A.pa + b, A.pb + b, A.partner + b, j, A.ng, A.head, A.c2d, A.theta, e);
+    m = wave_sum_i(m);
+    if (lane == 0) cnt[r] = (uint32_t)m;
 }
 
+// Same assignment; each chunk of 64 records writes at the row offset plus
+// the exclusive prefix of the lanes' counts, so cells stay in record order.
 __global__ __launch_bounds__(256) void rebin_fill(RebinArgs A, const int64_t *rowptr, uint32_t *ids)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (r >= A.nrays) return;
-    rebin_ray(A, r, rowptr, ids);
+    const int64_t b = A.segptr[r], n = A.segptr[r + 1] - b;
+    int64_t at = rowptr[r];
+    for (int64_t j0 = 0; j0 < n; j0 += 64) {
+        const int64_t j = j0 + lane;
+        CountEmit ce;
+        const int m = j < n ? seg::rebin_record(A.sr + b, A.pa + b, A.pb + b, A.partner + b, j, A.ng, A.head, A.c2d,
+                                                A.theta, ce)
+                            : 0;
+        int incl = m;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (j < n) {
+            WriteEmit we{ids, at + incl - m};
+            seg::rebin_record(A.sr + b, A.pa + b, A.pb + b, A.partner + b, j, A.ng, A.head, A.c2d, A.theta, we);
+        }
+        at += __shfl(incl, 63, 64);
+    }
 }
 
 TraceGeo geometry_of(const uspg_coeffs *c)
@@ -249,7 +273,7 @@ int colour_segments(uspg_coeffs *c, hipStream_t s)
 {
     const int U = c->scan.det_u, V = c->scan.det_v;
     const int64_t nrays = c->nrays;
-    const unsigned blocks = (unsigned)((nrays + 255) / 256);
+    const unsigned wblocks = (unsigned)((nrays * 64 + 255) / 256);   // one wavefront per ray
     c->mark.assign((size_t)U * V, 0);
     c->view_nnz.clear();
     uint32_t *cnt = nullptr, *ids = nullptr;
@@ -267,7 +291,7 @@ int colour_segments(uspg_coeffs *c, hipStream_t s)
         if (hipMemsetAsync(mark, 0, (size_t)U * V, s) != hipSuccess) { rc = fail(USPG_E_HIP, "memset"); break; }
         for (int v = 0; v < c->scan.n_views && rc == USPG_OK; ++v) {
             const RebinArgs A = rebin_args(c, v);
-            hipLaunchKernelGGL(rebin_count, dim3(blocks), dim3(256), 0, s, A, cnt);
+            hipLaunchKernelGGL(rebin_count, dim3(wblocks), dim3(256), 0, s, A, cnt);
             if ((rc = exclusive_scan_u32_to_i64(cnt, rowptr, nrays, s)) != USPG_OK) break;
             int64_t nnz = 0;
             if (hipMemcpyAsync(&nnz, rowptr + nrays, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -285,7 +309,7 @@ int colour_segments(uspg_coeffs *c, hipStream_t s)
                     break;
                 }
             }
-            hipLaunchKernelGGL(rebin_fill, dim3(blocks), dim3(256), 0, s, A, rowptr, ids);
+            hipLaunchKernelGGL(rebin_fill, dim3(wblocks), dim3(256), 0, s, A, rowptr, ids);
             if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "rebin launch failed"); break; }
             rc = conflict_marks(rowptr, ids, nrays, nnz, c->g->ncells, U, mark, s);
         }

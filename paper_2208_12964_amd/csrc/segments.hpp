@@ -231,6 +231,30 @@ struct FillSink {
     }
 };
 
+// Cells of record j of a ray's row (records sr[0..n), partner indices
+// relative to the row) in the view of angle theta: calls emit(cell) for every
+// cell the record meets that its partner does not; returns their count.
+template <class Emit>
+USPG_HD int rebin_record(const uint32_t *sr, const double *pa, const double *pb, const int32_t *partner, int64_t j,
+                         const int32_t *ng_of, const int64_t *head, int64_t c2d, double theta, Emit &emit)
+{
+    const int ring = ring_of(sr[j]), slice = slice_of(sr[j]), ng = ng_of[ring];
+    int first, count, pf = 0, pc = 0;
+    rebin_range(ng, pa[j], pb[j], theta, first, count);
+    const int32_t pj = partner[j];
+    if (pj >= 0) rebin_range(ng, pa[pj], pb[pj], theta, pf, pc);
+    const int64_t base = (int64_t)slice * c2d + head[ring];
+    int m = 0;
+    for (int q = 0; q < count; ++q) {
+        int s = first + q;
+        if (s >= ng) s -= ng;
+        if (pc && in_range(s, pf, pc, ng)) continue;
+        emit(base + s);
+        ++m;
+    }
+    return m;
+}
+
 // Cells of one ray's re-binned row in a view (theta): calls emit(cell) for
 // every distinct cell, record by record; returns the count.
 template <class Emit>
@@ -238,20 +262,7 @@ USPG_HD int64_t rebin_cells(const uint32_t *sr, const double *pa, const double *
                             const int32_t *ng_of, const int64_t *head, int64_t c2d, double theta, Emit &emit)
 {
     int64_t m = 0;
-    for (int64_t j = 0; j < n; ++j) {
-        const int ring = ring_of(sr[j]), slice = slice_of(sr[j]), ng = ng_of[ring];
-        int first, count, pf = 0, pc = 0;
-        rebin_range(ng, pa[j], pb[j], theta, first, count);
-        if (partner[j] >= 0) rebin_range(ng, pa[partner[j]], pb[partner[j]], theta, pf, pc);
-        const int64_t base = (int64_t)slice * c2d + head[ring];
-        for (int q = 0; q < count; ++q) {
-            int s = first + q;
-            if (s >= ng) s -= ng;
-            if (pc && in_range(s, pf, pc, ng)) continue;
-            emit(base + s);
-            ++m;
-        }
-    }
+    for (int64_t j = 0; j < n; ++j) m += rebin_record(sr, pa, pb, partner, j, ng_of, head, c2d, theta, emit);
     return m;
 }
 
