@@ -232,6 +232,16 @@ def _dev_check(t: torch.Tensor, name: str):
         raise ValueError(f"{name} must be a contiguous device tensor")
 
 
+def _used_on(stream, *tensors):
+    """Tell torch's caching allocator that the library's work on `stream`
+    (None: the current stream) uses these tensors, so memory freed on the
+    host is not handed out again before that work has run."""
+    s = stream if stream is not None else torch.cuda.current_stream()
+    for t in tensors:
+        if t is not None:
+            t.record_stream(s)
+
+
 def mart(coeffs: Coeffs, proj: torch.Tensor, image: torch.Tensor, n_sweeps: int, beta: float,
          tol: float = 0.0, work: torch.Tensor | None = None, stream=None) -> int:
     """Sp-MART in place on ``image`` (paper numbering): ``mart_run``.
@@ -249,6 +259,8 @@ def mart(coeffs: Coeffs, proj: torch.Tensor, image: torch.Tensor, n_sweeps: int,
                           C.c_void_p(image.data_ptr()), C.c_void_p(work.data_ptr()),
                           work.numel() * work.element_size(), n_sweeps, beta, tol, C.byref(done),
                           C.c_void_p(_stream(stream))))
+    if stream is not None:
+        _used_on(stream, proj, image, work)
     return done.value
 
 
@@ -320,6 +332,8 @@ class Batch:
         works = works if works is not None else self.work_buffers(images[0].device)
         P, I, W, wb, sw, be = self._args(projs, images, works, sweeps, betas)
         _check(lib().mart_run_batch(self.handle, P, I, W, wb, sw, be, C.c_void_p(_stream(stream))))
+        if stream is not None:
+            _used_on(stream, *projs, *images, *works)
         self._keep = (works,)
         return works
 
@@ -371,6 +385,8 @@ class Engine:
                                        C.c_void_p(image.data_ptr()), C.c_void_p(work.data_ptr()),
                                        work.numel() * work.element_size(), int(n_sweeps), float(beta),
                                        C.c_void_p(_stream(stream)), C.byref(slot)))
+        # the engine's later step calls use these buffers on `stream`
+        _used_on(stream, proj, image, work)
         self._held[slot.value] = (coeffs, proj, image, work)
         return slot.value
 
