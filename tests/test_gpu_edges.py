@@ -1,0 +1,95 @@
+"""Degenerate and edge cases of the GPU path against the FP64 oracle: zero
+sweeps, one ring, one view, one detector pixel, rays that miss the grid,
+all-zero projections, a stopping rule met after the first sweep, and the
+literal scheme on a half-turn scan with three views."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def U():
+    assert torch.cuda.is_available()
+    import paper_2208_12964_amd as U
+    U.lib()
+    return U
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def check(U, w, P=None, dtype=torch.float64, tol=1e-10, rebin=False):
+    P = synth.make_projections(w) if P is None else P
+    img, _, g, co = U.reconstruct(w, torch.as_tensor(P, device=dev()), dtype=dtype)
+    o = Oracle(w, nthreads=NTHREADS)
+    f_ref, _, lat = o.reconstruct_rebin(P) if rebin else o.reconstruct(P)
+    assert co.lattice == lat
+    f = img.cpu().numpy().astype(np.float64)
+    scale = max(np.max(np.abs(f_ref)), 1e-300)
+    assert np.max(np.abs(f - f_ref)) / scale <= tol, w.name
+    return f, f_ref
+
+
+def test_zero_sweeps_leave_the_image(U):
+    w = synth.small_cone("e-zero", n_rings=6, n_views=4, det=8, m=4)
+    g = U.Grid.from_workload(w)
+    co = U.Coeffs.from_workload(g, w)
+    img = torch.rand(g.n_cells, device=dev()) + 0.5
+    keep = img.clone()
+    assert U.mart(co, torch.ones(w.n_views * w.n_rays, device=dev()), img, 0, 0.1) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(img, keep)
+
+
+@pytest.mark.parametrize("w", [
+    synth.parallel("e-1ring", 1, 4, 6, 8, phantom="ellipses", sweeps=3),
+    synth.parallel("e-1view", 8, 1, 16, 8, phantom="ellipses", sweeps=3).with_(span=2 * math.pi),
+    synth.parallel("e-1ray", 8, 4, 1, 8, phantom="ellipses", sweeps=3),
+    synth.small_cone("e-cone-1ring", n_rings=1, n_views=4, det=4, m=4, n_slices=3, sweeps=2),
+    synth.small_cone("e-cone-1px", n_rings=5, n_views=4, det=1, m=4, n_slices=4, sweeps=2),
+], ids=lambda w: w.name)
+def test_tiny_grids_and_scans(U, w):
+    check(U, w)
+    check(U, w, dtype=torch.float32, tol=1e-4)
+
+
+def test_rays_missing_the_grid_and_zero_data(U):
+    # a fan twice as wide as the disk: the outer half of the rays miss it
+    w = synth.small_cone("e-wide", n_rings=8, n_views=4, det=20, m=4).with_(
+        geometry="fan2d", n_slices=1, height=0.0, det_v=1)
+    w = w.with_(det_half_u=2 * w.det_half_u)
+    check(U, w)
+    # all-zero data: every ray multiplies its cells by 1 - beta
+    Z = np.zeros((w.n_views, 1, w.det_u))
+    f, f_ref = check(U, w, P=Z)
+    assert np.all(f < 1.0) and np.all(f > 0.0)
+
+
+def test_stop_after_first_sweep(U):
+    w = synth.small_cone("e-stop", n_rings=6, n_views=4, det=8, m=4)
+    g = U.Grid.from_workload(w)
+    co = U.Coeffs.from_workload(g, w, torch.float64)
+    P = torch.as_tensor(synth.make_projections(w), device=dev())
+    img = torch.ones(g.n_cells, dtype=torch.float64, device=dev())
+    assert U.mart(co, P, img, 10, 0.1, tol=1e9) == 1
+    ref = torch.ones(g.n_cells, dtype=torch.float64, device=dev())
+    U.mart(co, P, ref, 1, 0.1)
+    torch.cuda.synchronize()
+    assert torch.equal(img, ref)
+
+
+def test_literal_scheme_half_turn_three_views(U):
+    w = synth.parallel("e-lit-half", 10, 3, 24, 1, phantom="ellipses", sweeps=4).with_(
+        sector_rule="paper", rebin=True, binary=True)
+    check(U, w, rebin=True)
+    check(U, w, dtype=torch.float32, tol=1e-4, rebin=True)
