@@ -260,7 +260,8 @@ def bench_serve(args):
 
 def bench_paper(args):
     """The paper's own scans (Table 1: fan beam 256^2 / 512^2 / 1024^2 with
-    50 views, cone beam 128^3 with 70 views) with its literal scheme:
+    50 views, cone beam 128^3 with 70 views; Table 3's Cu-lump and frog
+    geometries with synthetic phantoms) with its literal scheme:
     segment records re-binned per view, binary MART, bijection remap, and
     MAE / RMSE / SSIM against the phantom on the Cartesian grid.
     value = ray-cell updates/s of the 128^3 cone-beam solve."""
@@ -274,7 +275,8 @@ def bench_paper(args):
     say = lambda m: print(m, file=sys.stderr, flush=True)   # noqa: E731
     out_cfg = []
     head = None
-    for name in ("paper-fan-256-50v", "paper-fan-512-50v", "paper-fan-1024-50v", "paper-cone-128-70v"):
+    for name in ("paper-fan-256-50v", "paper-fan-512-50v", "paper-fan-1024-50v", "paper-culump-geometry",
+                 "paper-frog-geometry", "paper-cone-128-70v"):
         w = synth.get(name)
         if args.sweeps:
             w = w.with_(sweeps=args.sweeps)

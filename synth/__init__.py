@@ -7,7 +7,7 @@ HIP library consume the arrays it writes, so it must not depend on either.
 """
 
 from .workloads import (  # noqa: F401
-    Workload, WORKLOADS, get, small_cone, cone, parallel, batch2d_members, serve_request, paper_fan, paper_cone,
+    Workload, WORKLOADS, get, small_cone, cone, parallel, batch2d_members, serve_request, paper_fan, paper_cone, paper_specimen,
 )
 from .phantoms import (  # noqa: F401
     draw_phantom,

@@ -16,7 +16,8 @@ sees the same arrays:
   inclusions read 5.0.
 
 The draws describe a unit disk (a cylinder of half-height 1); they are
-scaled by the workload's radius in x, y and by its half-height in z.
+scaled by the workload's radius in x, y and by its half-height in z, times
+its phantom_scale.
 
 Noise: P <- max(P + sigma * max(P) * N(0, 1), 0), drawn in array order.
 """
@@ -73,8 +74,8 @@ def draw_phantom(w: Workload) -> list:
         raise ValueError(f"unknown phantom {w.phantom!r}")
     # the draws describe a unit disk / a cylinder of half-height 1: scale to
     # the workload's radius and half-height (identity for R = 1, H = 2)
-    sr = w.radius
-    sz = w.height / 2 if w.height > 0 else 1.0
+    sr = w.radius * w.phantom_scale
+    sz = (w.height / 2 if w.height > 0 else 1.0) * w.phantom_scale
     if sr != 1.0 or sz != 1.0:
         scale = np.array([sr, sr, sz])
         objs = [(cen * scale, ax * scale, ang, mu) for cen, ax, ang, mu in objs]

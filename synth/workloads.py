@@ -46,6 +46,7 @@ class Workload:
     binary: bool = False
     rebin: bool = False           # the paper's literal scheme: segment records re-binned per view
     quarter: bool = False         # literal scheme: trace one detector quadrant, mirror the rest
+    phantom_scale: float = 1.0    # phantom size relative to the grid (field of view smaller than the grid)
     phantom: str = "ellipses"     # "ellipses" | "ellipsoids" | "body_inclusions" | "none"
     n_objects: int = 6
     seed: int = 1
@@ -125,6 +126,33 @@ def paper_cone(n_cart: int, n_views: int = 70, **kw) -> Workload:
         sweeps=kw.pop("sweeps", 20), beta=kw.pop("beta", 0.4), remap_nc=n_cart, **kw)
 
 
+def paper_specimen(which: str, **kw) -> Workload:
+    """The geometry of the paper's two experimental scans (Table 3) with a
+    synthetic phantom in place of the specimen: Cu lump (source (-8.2, 0, 0),
+    detector centre (38.4, 0, 0), 128^3 grid of spacing 0.03125, 101 x 101
+    detectors 0.121 apart, 50 views) and frog (source (-22.5, 0, 0),
+    detector centre (24.1, 0, 0), 256^3 grid of spacing 0.0078, 201 x 201
+    detectors 0.06 apart, 70 views); relaxation 0.4, literal scheme, paper
+    grid with N / 2 rings and N slices, the cylinder inscribed in the cube.
+    The Cu-lump scan sees only the central 1.07 of the 2.0 radius, so its
+    phantom is drawn at 0.4 of the grid's size."""
+    if which == "culump":
+        n, h, det, pitch, p, dso, dsd = 128, 0.03125, 101, 0.121, 50, 8.2, 46.6
+    elif which == "frog":
+        n, h, det, pitch, p, dso, dsd = 256, 0.0078, 201, 0.06, 70, 22.5, 46.6
+    else:
+        raise ValueError(which)
+    R = n * h / 2
+    return Workload(
+        name=kw.pop("name", f"paper-{which}-geometry"), geometry="cone3d", n_rings=n // 2, n_slices=n, radius=R,
+        height=2 * R, sector_rule="paper", sector_multiple=1, n_views=p, span=2 * math.pi, det_u=det, det_v=det,
+        det_half_u=det * pitch / 2, det_half_v=det * pitch / 2, src_axis=dso, src_det=dsd, binary=True,
+        rebin=True, quarter=kw.pop("quarter", True), phantom=kw.pop("phantom", "ellipsoids"),
+        phantom_scale=kw.pop("phantom_scale", 1.0 if which == "frog" else 0.4),
+        n_objects=kw.pop("n_objects", 10), seed=kw.pop("seed", 47 if which == "frog" else 45),
+        sweeps=kw.pop("sweeps", 20), beta=kw.pop("beta", 0.4), remap_nc=n, **kw)
+
+
 WORKLOADS = {
     # 2D parallel beam, FP64 plain MART: 32 rings, 8 views over 180 degrees, 64 bins.
     # Sector counts are multiples of 16 so that the 22.5-degree view step is a
@@ -145,6 +173,8 @@ WORKLOADS = {
     "paper-fan-512-50v": paper_fan(512),
     "paper-fan-1024-50v": paper_fan(1024),
     "paper-cone-128-70v": paper_cone(128),
+    "paper-culump-geometry": paper_specimen("culump"),
+    "paper-frog-geometry": paper_specimen("frog"),
 }
 
 
