@@ -250,7 +250,7 @@ int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *sc, void *stream
         uspg_free_coeffs(c);
         return rc;
     }
-    c->device_bytes = (int64_t)(c->rowptr.bytes + c->ids.bytes + c->a.bytes + c->d_kq.bytes +
+    c->device_bytes = (int64_t)(c->rowptr.bytes + c->coef.bytes + c->d_kq.bytes +
                                 c->d_hq.bytes + c->d_ring_of_off.bytes);
     *out = c;
     return USPG_OK;
@@ -297,13 +297,16 @@ int uspg_coeffs_row(const uspg_coeffs *c, int32_t view, int64_t ray, int64_t *ce
     if (len == 0) return USPG_OK;
     if (!cells || !lengths) return fail(USPG_E_ARG, "null output");
     std::vector<uint32_t> ids(len);
-    USPG_HIP(hipMemcpy(ids.data(), c->ids.as<uint32_t>() + rp[0], sizeof(uint32_t) * len, hipMemcpyDeviceToHost));
     if (c->scan.coeff_dtype == USPG_F64) {
-        USPG_HIP(hipMemcpy(lengths, c->a.as<double>() + rp[0], sizeof(double) * len, hipMemcpyDeviceToHost));
+        std::vector<Coef<double>> pr(len);
+        USPG_HIP(hipMemcpy(pr.data(), c->coef.as<Coef<double>>() + rp[0], sizeof(Coef<double>) * len,
+                           hipMemcpyDeviceToHost));
+        for (int j = 0; j < len; ++j) { ids[j] = pr[j].id; lengths[j] = pr[j].a; }
     } else {
-        std::vector<float> a(len);
-        USPG_HIP(hipMemcpy(a.data(), c->a.as<float>() + rp[0], sizeof(float) * len, hipMemcpyDeviceToHost));
-        for (int j = 0; j < len; ++j) lengths[j] = a[j];
+        std::vector<Coef<float>> pr(len);
+        USPG_HIP(hipMemcpy(pr.data(), c->coef.as<Coef<float>>() + rp[0], sizeof(Coef<float>) * len,
+                           hipMemcpyDeviceToHost));
+        for (int j = 0; j < len; ++j) { ids[j] = pr[j].id; lengths[j] = pr[j].a; }
     }
     const uspg_grid *g = c->g;
     for (int j = 0; j < len; ++j) {
@@ -336,8 +339,7 @@ void uspg_free_coeffs(uspg_coeffs *c)
 {
     if (!c) return;
     c->rowptr.release();
-    c->ids.release();
-    c->a.release();
+    c->coef.release();
     c->d_kq.release();
     c->d_hq.release();
     c->d_ring_of_off.release();

@@ -57,8 +57,7 @@ constexpr int kMaxBatch = 96;     // problems per launch (kernel-argument space)
 
 struct ProblemStatic {
     const int64_t *rowptr;
-    const uint32_t *ids;
-    const void *a;
+    const void *coef;     // Coef<TC> pairs
     int64_t nrays;
     uint32_t Wc, Wtot;
     int U, Ku, Kv, n_views, lds;
@@ -88,7 +87,7 @@ __global__ void mart_multi(MultiArgs<T> A)
     const ProblemStatic S = A.st[A.first + blockIdx.x];
     const ProblemDyn<T> D = A.dyn[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const TC *a = static_cast<const TC *>(S.a);
+    const Coef<TC> *co = static_cast<const Coef<TC> *>(S.coef);
     if (S.lds) {
         for (uint32_t i = threadIdx.x; i < S.Wtot; i += blockDim.x) lds[i] = D.f[i];
         __syncthreads();
@@ -109,9 +108,9 @@ __global__ void mart_multi(MultiArgs<T> A)
                     const int n = (int)(S.rowptr[r + 1] - beg);
                     if (n == 0) continue;
                     if (S.lds)
-                        mart_row<T, TC, MAXC>(lds, shift, S.Wtot, D.beta, S.ids + beg, a + beg, n, Pv[r], lane);
+                        mart_row<T, TC, MAXC>(lds, shift, S.Wtot, D.beta, co + beg, n, Pv[r], lane);
                     else
-                        mart_row<T, TC, MAXC>(D.f, shift, S.Wtot, D.beta, S.ids + beg, a + beg, n, Pv[r], lane);
+                        mart_row<T, TC, MAXC>(D.f, shift, S.Wtot, D.beta, co + beg, n, Pv[r], lane);
                 }
                 __syncthreads();
             }
@@ -154,7 +153,7 @@ __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, co
     const int len = (int)(S.rowptr[r + 1] - beg);
     if (len == 0) return;
     const uint32_t shift = (uint32_t)(((uint64_t)v * S.Wc) % S.Wtot);
-    mart_row<T, TC, MAXC>(D.f, shift, S.Wtot, D.beta, S.ids + beg, static_cast<const TC *>(S.a) + beg, len,
+    mart_row<T, TC, MAXC>(D.f, shift, S.Wtot, D.beta, static_cast<const Coef<TC> *>(S.coef) + beg, len,
                           D.P[(int64_t)v * S.nrays + r], threadIdx.x & 63);
 }
 
@@ -286,8 +285,7 @@ ProblemStatic static_of(const uspg_coeffs *c)
 {
     ProblemStatic p;
     p.rowptr = c->rowptr.as<int64_t>();
-    p.ids = c->ids.as<uint32_t>();
-    p.a = c->a.p;
+    p.coef = c->coef.p;
     p.nrays = c->nrays;
     p.Wc = (uint32_t)c->Wc;
     p.Wtot = (uint32_t)c->Wtot;

@@ -14,16 +14,16 @@
 namespace uspg {
 namespace {
 
-__global__ __launch_bounds__(256) void count_cells(const int64_t *rowptr, const uint32_t *ids,
+__global__ __launch_bounds__(256) void count_cells(const int64_t *rowptr, const uint32_t *ids, int stride,
                                                    int64_t nrays, uint32_t *cnt)
 {
     int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
     if (r >= nrays) return;
-    for (int64_t j = rowptr[r] + lane; j < rowptr[r + 1]; j += 64) atomicAdd(&cnt[ids[j]], 1u);
+    for (int64_t j = rowptr[r] + lane; j < rowptr[r + 1]; j += 64) atomicAdd(&cnt[ids[j * stride]], 1u);
 }
 
-__global__ __launch_bounds__(256) void fill_cells(const int64_t *rowptr, const uint32_t *ids,
+__global__ __launch_bounds__(256) void fill_cells(const int64_t *rowptr, const uint32_t *ids, int stride,
                                                   int64_t nrays, const uint32_t *cptr,
                                                   uint32_t *cur, uint32_t *rays)
 {
@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void fill_cells(const int64_t *rowptr, const u
     int lane = threadIdx.x & 63;
     if (r >= nrays) return;
     for (int64_t j = rowptr[r] + lane; j < rowptr[r + 1]; j += 64) {
-        uint32_t c = ids[j];
+        uint32_t c = ids[j * stride];
         uint32_t pos = atomicAdd(&cur[c], 1u);
         rays[cptr[c] + pos] = (uint32_t)r;
     }
@@ -67,8 +67,8 @@ bool lattice_ok(const std::vector<uint8_t> &mark, int U, int V, int ku, int kv)
 
 }  // namespace
 
-int conflict_marks(const int64_t *rowptr, const uint32_t *ids, int64_t nrays, int64_t nnz, int64_t ncells,
-                   int U, uint8_t *mark, hipStream_t s)
+int conflict_marks(const int64_t *rowptr, const uint32_t *ids, int stride, int64_t nrays, int64_t nnz,
+                   int64_t ncells, int U, uint8_t *mark, hipStream_t s)
 {
     uint32_t *cnt = nullptr, *cptr = nullptr, *rays = nullptr;
     int rc = USPG_OK;
@@ -84,13 +84,13 @@ int conflict_marks(const int64_t *rowptr, const uint32_t *ids, int64_t nrays, in
             break;
         }
         const unsigned rb = (unsigned)((nrays * 64 + 255) / 256);
-        hipLaunchKernelGGL(count_cells, dim3(rb), dim3(256), 0, s, rowptr, ids, nrays, cnt);
+        hipLaunchKernelGGL(count_cells, dim3(rb), dim3(256), 0, s, rowptr, ids, stride, nrays, cnt);
         if ((rc = exclusive_scan_u32(cnt, cptr, ncells, s)) != USPG_OK) break;
         if (hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (ncells + 1), s) != hipSuccess) {
             rc = fail(USPG_E_HIP, "colouring: memset failed");
             break;
         }
-        hipLaunchKernelGGL(fill_cells, dim3(rb), dim3(256), 0, s, rowptr, ids, nrays, cptr, cnt, rays);
+        hipLaunchKernelGGL(fill_cells, dim3(rb), dim3(256), 0, s, rowptr, ids, stride, nrays, cptr, cnt, rays);
         hipLaunchKernelGGL(pair_offsets, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, s,
                            cptr, rays, ncells, U, mark);
         if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "colouring: launch failed"); break; }
@@ -135,9 +135,12 @@ int colour_reference_view(uspg_coeffs *c, hipStream_t s)
     if (hipMalloc((void **)&mark, (size_t)U * V) != hipSuccess) return fail(USPG_E_NOMEM, "colouring: allocation");
     int rc = USPG_OK;
     if (hipMemsetAsync(mark, 0, (size_t)U * V, s) != hipSuccess) rc = fail(USPG_E_HIP, "colouring: memset failed");
-    // ids live in the device layout
+    // ids live in the device layout, as the first word of each (id,
+    // coefficient) pair
+    const int stride = (int)((c->scan.coeff_dtype == USPG_F64 ? sizeof(Coef<double>) : sizeof(Coef<float>)) / 4);
     if (rc == USPG_OK)
-        rc = conflict_marks(c->rowptr.as<int64_t>(), c->ids.as<uint32_t>(), c->nrays, c->nnz, c->Wtot, U, mark, s);
+        rc = conflict_marks(c->rowptr.as<int64_t>(), c->coef.as<uint32_t>(), stride, c->nrays, c->nnz, c->Wtot, U,
+                            mark, s);
     if (rc == USPG_OK && hipMemcpy(c->mark.data(), mark, (size_t)U * V, hipMemcpyDeviceToHost) != hipSuccess)
         rc = fail(USPG_E_HIP, "colouring: copy failed");
     (void)hipFree(mark);

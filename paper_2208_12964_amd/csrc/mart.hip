@@ -52,8 +52,7 @@ int grid_cap()
 template <class T, class TC>
 struct BatchArgs {
     const int64_t *rowptr;
-    const uint32_t *ids;
-    const TC *a;
+    const Coef<TC> *co;
     const T *P;        // projections of the view, [rays]
     T *f;              // wedge-major image
     uint32_t shift;    // v * Wc (mod Wtot)
@@ -87,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
         const int64_t beg = A.rowptr[r];
         const int n = (int)(A.rowptr[r + 1] - beg);
         if (n == 0) continue;
-        mart_row<T, TC, MAXC>(A.f, A.shift, A.wtot, A.beta, A.ids + beg, A.a + beg, n, A.P[r], lane);
+        mart_row<T, TC, MAXC>(A.f, A.shift, A.wtot, A.beta, A.co + beg, n, A.P[r], lane);
     }
 }
 
@@ -274,8 +273,7 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
 
     BatchArgs<T, TC> A{};
     A.rowptr = c->rowptr.as<int64_t>();
-    A.ids = c->ids.as<uint32_t>();
-    A.a = c->a.as<TC>();
+    A.co = c->coef.as<Coef<TC>>();
     A.f = nat;
     A.wtot = (uint32_t)c->Wtot;
     A.U = c->scan.det_u;

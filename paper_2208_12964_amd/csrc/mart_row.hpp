@@ -1,8 +1,9 @@
 // Per-ray Sp-MART update shared by the single-problem and batched kernels
 // (Sec. III.D, eqs. 17-18).  One wavefront handles one ray: coefficients are
-// loaded with non-temporal hints, the ids rotated to the view by one add and
-// a conditional subtract, the image gathered through `img` (global memory or
-// LDS), Pbar and a_max reduced across the wavefront in a fixed order, then
+// loaded as (id, coefficient) pairs with non-temporal hints, the ids rotated
+// to the view by one add and a conditional subtract, the image gathered
+// through `img` (global memory or LDS), Pbar and a_max reduced across the
+// wavefront in a fixed order, then
 //   f_j <- f_j (1 + beta (P / Pbar - 1) a_j / a_max).
 #pragma once
 
@@ -38,13 +39,31 @@ __device__ __forceinline__ T fmadd(T a, T b, T c) { return __builtin_fma(a, b, c
 template <>
 __device__ __forceinline__ float fmadd<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Non-temporal load of one (id, coefficient) pair: one vector load.
+__device__ __forceinline__ void load_coef(const Coef<float> *p, uint32_t &id, float &a)
+{
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 e = __builtin_nontemporal_load(reinterpret_cast<const u2 *>(p));
+    id = e.x;
+    a = __uint_as_float(e.y);
+}
+
+__device__ __forceinline__ void load_coef(const Coef<double> *p, uint32_t &id, double &a)
+{
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const u4 e = __builtin_nontemporal_load(reinterpret_cast<const u4 *>(p));
+    id = e.x;
+    const unsigned long long bits = ((unsigned long long)e.w << 32) | e.z;
+    __builtin_memcpy(&a, &bits, sizeof(a));
+}
+
 // One row of C chunks of 64 coefficients, kept in registers.  Indices are
 // clamped and coefficients masked instead of branching, so every load of a
 // phase is issued before the first wait: the ids and coefficients, then all
 // gathers, then the reductions, then the predicated scatter.
 template <class T, class TC, int C, class Img>
 __device__ __forceinline__ void row_in_registers(Img img, uint32_t shift, uint32_t wtot, T beta,
-                                                 const uint32_t *ids, const TC *a, int n, T P, int lane)
+                                                 const Coef<TC> *co, int n, T P, int lane)
 {
 #pragma clang fp contract(off)
     uint32_t id[C];
@@ -56,9 +75,12 @@ __device__ __forceinline__ void row_in_registers(Img img, uint32_t shift, uint32
         const int jj = j < n ? j : last;
         // the coefficient stream is read once per view: non-temporal loads
         // keep it from evicting the image from the caches
-        const uint32_t t = __builtin_nontemporal_load(ids + jj) + shift;
+        uint32_t cid;
+        TC ca;
+        load_coef(co + jj, cid, ca);
+        const uint32_t t = cid + shift;
         id[k] = t >= wtot ? t - wtot : t;
-        av[k] = (T)__builtin_nontemporal_load(a + jj) * (j < n ? T(1) : T(0));   // masked, not branched
+        av[k] = (T)ca * (j < n ? T(1) : T(0));   // masked, not branched
     }
 #pragma unroll
     for (int k = 0; k < C; ++k) fv[k] = img[id[k]];
@@ -80,15 +102,15 @@ __device__ __forceinline__ void row_in_registers(Img img, uint32_t shift, uint32
 
 // Rows longer than the register path: forward pass, then re-read and update.
 template <class T, class TC, class Img>
-__device__ void row_streamed(Img img, uint32_t shift, uint32_t wtot, T beta, const uint32_t *ids,
-                             const TC *a, int n, T P, int lane)
+__device__ void row_streamed(Img img, uint32_t shift, uint32_t wtot, T beta, const Coef<TC> *co, int n, T P,
+                             int lane)
 {
 #pragma clang fp contract(off)
     T acc = T(0), amax = T(0);
     for (int j = lane; j < n; j += 64) {
-        uint32_t t = ids[j] + shift;
+        uint32_t t = co[j].id + shift;
         t = t >= wtot ? t - wtot : t;
-        T av = (T)a[j];
+        T av = (T)co[j].a;
         acc = fmadd(av, img[t], acc);
         amax = av > amax ? av : amax;
     }
@@ -97,28 +119,28 @@ __device__ void row_streamed(Img img, uint32_t shift, uint32_t wtot, T beta, con
     if (!(acc > T(0)) || !(amax > T(0))) return;
     const T c = beta * (P / acc - T(1)) / amax;
     for (int j = lane; j < n; j += 64) {
-        uint32_t t = ids[j] + shift;
+        uint32_t t = co[j].id + shift;
         t = t >= wtot ? t - wtot : t;
-        img[t] = img[t] * fmadd(c, (T)a[j], T(1));
+        img[t] = img[t] * fmadd(c, (T)co[j].a, T(1));
     }
 }
 
 // One ray: dispatch on its wave-uniform chunk count to a compile-time
 // unrolled register body (rows longer than 64 * MAXC are streamed).
 template <class T, class TC, int MAXC, class Img>
-__device__ __forceinline__ void mart_row(Img img, uint32_t shift, uint32_t wtot, T beta, const uint32_t *ids,
-                                         const TC *a, int n, T P, int lane)
+__device__ __forceinline__ void mart_row(Img img, uint32_t shift, uint32_t wtot, T beta, const Coef<TC> *co, int n,
+                                         T P, int lane)
 {
     const int chunks = (n + 63) >> 6;   // wave-uniform
     if (chunks > MAXC) {
-        row_streamed<T, TC>(img, shift, wtot, beta, ids, a, n, P, lane);
+        row_streamed<T, TC>(img, shift, wtot, beta, co, n, P, lane);
         return;
     }
     switch (chunks) {
 #define USPG_ROW_CASE(C)                                                                          \
     case C:                                                                                       \
         if (C <= MAXC)                                                                            \
-            row_in_registers<T, TC, (C <= MAXC ? C : 1)>(img, shift, wtot, beta, ids, a, n, P, lane); \
+            row_in_registers<T, TC, (C <= MAXC ? C : 1)>(img, shift, wtot, beta, co, n, P, lane); \
         break;
         USPG_ROW_CASE(1) USPG_ROW_CASE(2) USPG_ROW_CASE(3) USPG_ROW_CASE(4)
         USPG_ROW_CASE(5) USPG_ROW_CASE(6) USPG_ROW_CASE(7) USPG_ROW_CASE(8)

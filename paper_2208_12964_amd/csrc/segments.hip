@@ -311,7 +311,7 @@ int colour_segments(uspg_coeffs *c, hipStream_t s)
             }
             hipLaunchKernelGGL(rebin_fill, dim3(wblocks), dim3(256), 0, s, A, rowptr, ids);
             if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "rebin launch failed"); break; }
-            rc = conflict_marks(rowptr, ids, nrays, nnz, c->g->ncells, U, mark, s);
+            rc = conflict_marks(rowptr, ids, 1, nrays, nnz, c->g->ncells, U, mark, s);
         }
         if (rc != USPG_OK) break;
         if (hipMemcpy(c->mark.data(), mark, (size_t)U * V, hipMemcpyDeviceToHost) != hipSuccess)

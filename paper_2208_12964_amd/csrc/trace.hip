@@ -54,6 +54,17 @@ __global__ __launch_bounds__(256) void trace_fill(TraceGeo G, int64_t nrays, con
     w.run();
 }
 
+template <class TC>
+__global__ __launch_bounds__(256) void interleave_coef(const uint32_t *ids, const TC *a, int64_t n, Coef<TC> *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Coef<TC> e{};
+    e.id = ids[i];
+    e.a = a[i];
+    out[i] = e;
+}
+
 __global__ void row_lengths_max(const uint32_t *cnt, int64_t n, unsigned int *mx)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,18 +115,38 @@ int trace_reference_view(uspg_coeffs *c, hipStream_t s)
         if (nnz >= (int64_t)UINT32_MAX) { rc = fail(USPG_E_ARG, "more than 2^32 reference coefficients"); break; }
         c->nnz = nnz;
         c->max_row = (int32_t)mrow;
-        size_t asz = sc.coeff_dtype == USPG_F64 ? sizeof(double) : sizeof(float);
-        if ((rc = c->ids.alloc(sizeof(uint32_t) * (nnz > 0 ? nnz : 1))) != USPG_OK) break;
-        if ((rc = c->a.alloc(asz * (nnz > 0 ? nnz : 1))) != USPG_OK) break;
+        // the walk writes ids and coefficients as two arrays, then they are
+        // interleaved into the (id, coefficient) pairs the kernels read
+        const bool f64 = sc.coeff_dtype == USPG_F64;
+        const size_t asz = f64 ? sizeof(double) : sizeof(float);
+        const int64_t n1 = nnz > 0 ? nnz : 1;
+        DevBuf ids, a;
+        if ((rc = ids.alloc(sizeof(uint32_t) * n1)) != USPG_OK) break;
+        if ((rc = a.alloc(asz * n1)) != USPG_OK) { ids.release(); break; }
+        if ((rc = c->coef.alloc((f64 ? sizeof(Coef<double>) : sizeof(Coef<float>)) * n1)) != USPG_OK) {
+            ids.release();
+            a.release();
+            break;
+        }
         int binary = sc.weights == USPG_WEIGHTS_BINARY;
-        if (sc.coeff_dtype == USPG_F64)
+        const unsigned eb = (unsigned)((n1 + 255) / 256);
+        if (f64) {
             hipLaunchKernelGGL(trace_fill<double>, dim3(blocks), dim3(256), 0, s, G, nrays,
-                               c->rowptr.as<int64_t>(), c->ids.as<uint32_t>(), c->a.as<double>(), binary);
-        else
+                               c->rowptr.as<int64_t>(), ids.as<uint32_t>(), a.as<double>(), binary);
+            hipLaunchKernelGGL(interleave_coef<double>, dim3(eb), dim3(256), 0, s, ids.as<uint32_t>(), a.as<double>(),
+                               nnz, c->coef.as<Coef<double>>());
+        } else {
             hipLaunchKernelGGL(trace_fill<float>, dim3(blocks), dim3(256), 0, s, G, nrays,
-                               c->rowptr.as<int64_t>(), c->ids.as<uint32_t>(), c->a.as<float>(), binary);
-        if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "trace_fill launch failed"); break; }
-        if (hipStreamSynchronize(s) != hipSuccess) { rc = fail(USPG_E_HIP, "trace_fill failed"); break; }
+                               c->rowptr.as<int64_t>(), ids.as<uint32_t>(), a.as<float>(), binary);
+            hipLaunchKernelGGL(interleave_coef<float>, dim3(eb), dim3(256), 0, s, ids.as<uint32_t>(), a.as<float>(),
+                               nnz, c->coef.as<Coef<float>>());
+        }
+        const bool launched = hipGetLastError() == hipSuccess;
+        const bool synced = hipStreamSynchronize(s) == hipSuccess;
+        ids.release();
+        a.release();
+        if (!launched) { rc = fail(USPG_E_HIP, "trace_fill launch failed"); break; }
+        if (!synced) { rc = fail(USPG_E_HIP, "trace_fill failed"); break; }
     } while (0);
     (void)hipFree(cnt);
     (void)hipFree(mx);

@@ -24,6 +24,19 @@ int fail(int code, const std::string &msg);
             return ::uspg::fail(USPG_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// One stored coefficient: the cell id in the device layout and the value,
+// interleaved so that a row is read with one vector load per entry.
+template <class TC> struct Coef;
+template <> struct alignas(8) Coef<float> {
+    uint32_t id;
+    float a;
+};
+template <> struct alignas(16) Coef<double> {
+    uint32_t id;
+    uint32_t pad;
+    double a;
+};
+
 // Device buffer owned by a handle.
 struct DevBuf {
     void *p = nullptr;
@@ -69,8 +82,7 @@ struct uspg_coeffs {
     int Ku = 1, Kv = 1;
     std::vector<uint8_t> mark;    // conflict offsets [det_v][det_u]
     uspg::DevBuf rowptr;          // int64 [nrays + 1]
-    uspg::DevBuf ids;             // uint32 [nnz]
-    uspg::DevBuf a;               // float or double [nnz]
+    uspg::DevBuf coef;            // Coef<float or double> [nnz]: (cell id, coefficient) pairs
     uspg::DevBuf d_kq, d_hq;      // int32 [nr]
     uspg::DevBuf d_ring_of_off;   // int32 [Cq]: ring of each within-slice offset, -1 padding
     int64_t device_bytes = 0;
@@ -97,9 +109,10 @@ int trace_reference_view(uspg_coeffs *c, hipStream_t s);
 // colour.hip
 int colour_reference_view(uspg_coeffs *c, hipStream_t s);
 // ORs into mark (device, det_u * det_v bytes) the offsets of every pair of
-// rays of the CSR (ids < ncells) that share a cell; synchronises s.
-int conflict_marks(const int64_t *rowptr, const uint32_t *ids, int64_t nrays, int64_t nnz, int64_t ncells,
-                   int U, uint8_t *mark, hipStream_t s);
+// rays of the CSR that share a cell; entry j's cell id is ids[j * stride]
+// (< ncells); synchronises s.
+int conflict_marks(const int64_t *rowptr, const uint32_t *ids, int stride, int64_t nrays, int64_t nnz,
+                   int64_t ncells, int U, uint8_t *mark, hipStream_t s);
 // Smallest valid lattice for c->mark (or the requested one).
 int choose_lattice(uspg_coeffs *c);
 // segments.hip
