@@ -79,6 +79,37 @@ def parse():
     return ap.parse_args()
 
 
+def copy_bandwidth(dev, mib: int = 1024, reps: int = 5) -> float:
+    """Context for the roofline: GB/s (read + write bytes) of a plain device
+    copy of `mib` MiB, median of `reps` timed copies after a warm-up."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b) * 1e-3)
+    del src, dst
+    return 2.0 * (mib << 20) / sorted(times)[len(times) // 2] / 1e9
+
+
+def host_info() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
 def cpu_baseline(w, lattice, P, rows):
     """The FP64 oracle on a bounded sample of the same workload: the rays of
     `rows` central detector rows, traced, then MART over all views and sweeps
@@ -107,6 +138,7 @@ def cpu_baseline(w, lattice, P, rows):
     t2 = time.perf_counter()
     updates = w.n_views * csr.nnz * w.sweeps
     return {"value": updates / (t2 - t0), "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "host": host_info(),
             "sample": f"{rows} central detector rows ({len(rays)} rays, {csr.nnz} reference nonzeros) of "
                       f"{w.name}: trace {t1 - t0:.2f} s + {w.sweeps} MART sweeps over {w.n_views} views "
                       f"{t2 - t1:.2f} s, FP64"}
@@ -410,6 +442,7 @@ def main():
     bytes_per_launch = 16.0 * updates / n_launch
     achieved = bytes_per_launch / per_launch_s / 1e9
     traffic = counter_traffic()
+    copy_gbs = copy_bandwidth(dev)
     f = img.float().cpu().numpy()
     out = {
         "metric": "MART ray-cell updates/s", "value": updates / (ms_step * 1e-3), "unit": "updates/s",
@@ -425,7 +458,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "kernel": "mart_batch", "bytes_per_update": 16,
-                     "launches_per_step": n_launch, "avg_launch_us": per_launch_s * 1e6},
+                     "launches_per_step": n_launch, "avg_launch_us": per_launch_s * 1e6,
+                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None},
         "image": {"min": float(f.min()), "max": float(f.max())},
     }
     if not args.no_cpu_baseline:
