@@ -286,7 +286,10 @@ void uspg_free_batch(uspg_batch *b);
  * every uspg_engine_step call advances every admitted problem by n_steps
  * steps (one step = one (view, colour class) batch of Sec. III.D, in the
  * problem's own sweep > view > class order), with one launch per step
- * covering all of them.  A problem finishes after n_sweeps full sweeps;
+ * covering all of them, except that a problem whose largest class fills
+ * mart_run's capped grid on its own (16 workgroups of 256 threads per
+ * compute unit) gets its own mart_run launch per step.  A problem finishes
+ * after n_sweeps full sweeps;
  * the result of each problem is bit for bit the one mart_run gives for it
  * alone, whatever else shares the engine.
  * max_slots bounds the problems admitted at once; dtype is the image type

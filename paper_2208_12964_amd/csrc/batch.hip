@@ -129,7 +129,9 @@ template <class T, class TC, int MAXC>
 __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, const ProblemDyn<T> *dyn,
                                                      const int *wgbeg, int n, int step)
 {
-    const int b = blockIdx.x;
+    // each XCD takes a contiguous run of the virtual workgroups, as in the
+    // single-problem kernel
+    const int b = row::xcd_block(blockIdx.x, gridDim.x);
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -361,11 +363,14 @@ struct uspg_engine {
         const void *proj = nullptr;
         void *image = nullptr, *work = nullptr;
         int sweeps = 0, total = 0, groups = 0;
+        bool wide = false;                // its classes alone fill the capped grid
         int64_t offset = 0;
         double beta = 0;
     };
     std::vector<Slot> slots;
-    std::vector<int> active;              // slot ids in launch order
+    std::vector<int> active;              // slot ids in admission order
+    std::vector<int> table;               // the active slots of the lockstep launch
+    std::vector<int> wide;                // the active slots launched one by one
     int grid = 0;
     uspg::DevBuf d_static, d_dyn, d_wgbeg;
     void *h_stage = nullptr;              // pinned: static, dyn, wgbeg
@@ -378,17 +383,26 @@ namespace {
 
 constexpr int kEngineWaves = 4;
 
+// Problems whose largest class needs at least the single-problem kernel's
+// capped grid fill the chip alone: each of their steps is launched with that
+// kernel, one problem after another (measured on a 256-ring, 32-view cone:
+// two such problems in one lockstep launch took 272 us per step, two
+// single-problem launches 224 us).  The others share one lockstep launch.
+// Both kernels run the same row update, so the bits do not change.
 template <class T>
 int engine_upload(uspg_engine *e, hipStream_t s)
 {
     USPG_HIP(hipEventSynchronize(e->staged));
-    const int n = (int)e->active.size();
+    e->table.clear();
+    e->wide.clear();
+    for (int id : e->active) (e->slots[id].wide ? e->wide : e->table).push_back(id);
+    const int n = (int)e->table.size();
     auto *st = static_cast<ProblemStatic *>(e->h_stage);
     auto *dyn = reinterpret_cast<ProblemDyn<T> *>(st + e->max_slots);
     int *wg = reinterpret_cast<int *>(dyn + e->max_slots);
     wg[0] = 0;
     for (int j = 0; j < n; ++j) {
-        const uspg_engine::Slot &sl = e->slots[e->active[j]];
+        const uspg_engine::Slot &sl = e->slots[e->table[j]];
         st[j] = static_of(sl.c);
         dyn[j].P = static_cast<const T *>(sl.proj);
         dyn[j].f = static_cast<T *>(sl.work);
@@ -399,22 +413,37 @@ int engine_upload(uspg_engine *e, hipStream_t s)
         wg[j + 1] = wg[j] + sl.groups;
     }
     e->grid = wg[n];
-    USPG_HIP(hipMemcpyAsync(e->d_static.p, st, sizeof(ProblemStatic) * n, hipMemcpyHostToDevice, s));
-    USPG_HIP(hipMemcpyAsync(e->d_dyn.p, dyn, sizeof(ProblemDyn<T>) * n, hipMemcpyHostToDevice, s));
-    USPG_HIP(hipMemcpyAsync(e->d_wgbeg.p, wg, sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
+    if (n > 0) {
+        USPG_HIP(hipMemcpyAsync(e->d_static.p, st, sizeof(ProblemStatic) * n, hipMemcpyHostToDevice, s));
+        USPG_HIP(hipMemcpyAsync(e->d_dyn.p, dyn, sizeof(ProblemDyn<T>) * n, hipMemcpyHostToDevice, s));
+        USPG_HIP(hipMemcpyAsync(e->d_wgbeg.p, wg, sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
+    }
     USPG_HIP(hipEventRecord(e->staged, s));
     return USPG_OK;
 }
 
 // Offsets were uploaded relative to the engine's step count at this call,
-// so the launches of one call are numbered from 0.
+// so the launches of one call are numbered from 0.  Step t of a problem is
+// its step e->gstep + t - offset (view-major, class-minor, as in mart_run).
 template <class T, class TC, int MAXC>
 int engine_launch(uspg_engine *e, int steps, hipStream_t s)
 {
-    for (int t = 0; t < steps; ++t)
-        hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC>), dim3(e->grid), dim3(64 * kEngineWaves), 0, s,
-                           e->d_static.as<ProblemStatic>(), e->d_dyn.as<ProblemDyn<T>>(),
-                           e->d_wgbeg.as<int>(), (int)e->active.size(), t);
+    for (int t = 0; t < steps; ++t) {
+        if (!e->table.empty())
+            hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC>), dim3(e->grid), dim3(64 * kEngineWaves), 0, s,
+                               e->d_static.as<ProblemStatic>(), e->d_dyn.as<ProblemDyn<T>>(),
+                               e->d_wgbeg.as<int>(), (int)e->table.size(), t);
+        for (int id : e->wide) {
+            const uspg_engine::Slot &sl = e->slots[id];
+            const int64_t local = e->gstep + t - sl.offset;
+            if (local < 0 || local >= sl.total) continue;
+            const int K = sl.c->Ku * sl.c->Kv;
+            const int cl = (int)(local % K);
+            const int v = (int)((local / K) % sl.c->scan.n_views);
+            const int rc = batch_step(sl.c, e->dtype, sl.proj, sl.work, sl.beta, v, cl, s);
+            if (rc != USPG_OK) return rc;
+        }
+    }
     USPG_HIP(hipGetLastError());
     return USPG_OK;
 }
@@ -423,7 +452,7 @@ template <class T, class TC>
 int engine_maxc(uspg_engine *e, int steps, hipStream_t s)
 {
     int64_t longest = 0;
-    for (int id : e->active) longest = std::max<int64_t>(longest, e->slots[id].c->max_row);
+    for (int id : e->table) longest = std::max<int64_t>(longest, e->slots[id].c->max_row);
     const int64_t chunks = (longest + 63) / 64;
     if (chunks <= 2) return engine_launch<T, TC, 2>(e, steps, s);
     if (chunks <= 4) return engine_launch<T, TC, 4>(e, steps, s);
@@ -631,6 +660,7 @@ int uspg_engine_admit(uspg_engine *e, const uspg_coeffs *c, const void *proj, vo
     sl.sweeps = n_sweeps;
     sl.total = n_sweeps * c->scan.n_views * c->Ku * c->Kv;
     sl.groups = lockstep_groups(c, kEngineWaves);
+    sl.wide = sl.groups >= batch_grid_cap();
     sl.offset = e->gstep;
     sl.beta = beta;
     e->active.push_back(id);

@@ -23,6 +23,7 @@ namespace uspg {
 namespace {
 
 using row::mart_row;
+using row::xcd_block;
 using row::wave_max;
 using row::wave_sum;
 
@@ -61,16 +62,6 @@ struct BatchArgs {
     T beta;
 };
 
-// Workgroups are dispatched round robin over the 8 XCDs; renumber them so
-// that each XCD owns one contiguous run of the class's rays (neighbouring rays
-// touch neighbouring cells, which then share that XCD's L2).
-__device__ inline int xcd_block(int b, int nb)
-{
-    int xcd = b & 7, idx = b >> 3;
-    int per = nb >> 3, rem = nb & 7;
-    return xcd * per + (xcd < rem ? xcd : rem) + idx;
-}
-
 // The grid is capped (kBlocksPerCU workgroups per CU) and each wavefront
 // strides through the class by the grid's wavefront count; the rays of a
 // class share no cell, so the assignment changes no result.
@@ -91,12 +82,20 @@ __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
 }
 
 // The paper's literal variant: one (view, class) batch with each ray's row
-// rebuilt from its segment records (segments.hpp).  Lane j takes records j,
-// j + 64, ...; a record meets a run of sectors of one ring and slice, minus
-// those its partner record (the line's other pass through that ring and
-// slice) already met.  Binary coefficients: Pbar is the sum of f over the
-// row and every cell gets the same factor 1 + beta (P / Pbar - 1) (eq. 18
-// with a_j = a_max = 1).  The image is in the paper's numbering.
+// rebuilt from its segment records (segments.hpp).  A record meets a run of
+// sectors of one ring and slice, minus those its partner record (the line's
+// other pass through that ring and slice) already met.  Binary coefficients:
+// Pbar is the sum of f over the row and every cell gets the same factor
+// 1 + beta (P / Pbar - 1) (eq. 18 with a_j = a_max = 1).  The image is in the
+// paper's numbering.
+//
+// A group of G lanes (32 or 64, picked per coefficient set) takes one ray,
+// so a wavefront holds 64 / G rays;
+// lane l of a group takes records l, l + G, ...  The runs of a lane's first
+// kRebinNR records and up to kRebinNS of their gathered values stay in
+// registers between the gather and the scatter; what does not fit is
+// rebuilt in the second pass.  Every gather of the register part is issued
+// before the first wait (invalid entries read cell 0 and are masked).
 template <class T>
 struct RebinMartArgs {
     const int64_t *segptr;
@@ -112,6 +111,9 @@ struct RebinMartArgs {
     int U, cu, cw, Ku, Kv, nu, ncls, nblk;
     T beta;
 };
+
+constexpr int kRebinNR = 2;           // records per lane kept in registers
+constexpr int kRebinNS = 4;           // sectors per record kept in registers
 
 template <class T>
 struct SumEmit {
@@ -132,28 +134,93 @@ struct ScaleEmit {
     __device__ void operator()(int64_t cell) { f[cell] = f[cell] * g; }
 };
 
-template <class T>
+template <class V, int G>
+__device__ inline V group_sum(V v)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <class T, int G>
 __global__ __launch_bounds__(kBlock) void mart_rebin(RebinMartArgs<T> A)
 {
 #pragma clang fp contract(off)
+    constexpr int RPW = 64 / G;
+    constexpr int NR = kRebinNR, NS = kRebinNS;
     const int lane = threadIdx.x & 63;
-    const int x = xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6);
-    if (x >= A.ncls) return;
-    const int w = A.cw + (x / A.nu) * A.Kv;
-    const int u = A.cu + (x % A.nu) * A.Ku;
-    const int64_t r = (int64_t)w * A.U + u;
-    const int64_t b = A.segptr[r];
-    const int n = (int)(A.segptr[r + 1] - b);
-    if (n == 0) return;
+    const int sub = lane & (G - 1);
+    const int x = (xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6)) * RPW + lane / G;
+    int64_t r = 0, b = 0;
+    int n = 0;
+    if (x < A.ncls) {
+        const int w = A.cw + (x / A.nu) * A.Kv;
+        const int u = A.cu + (x % A.nu) * A.Ku;
+        r = (int64_t)w * A.U + u;
+        b = A.segptr[r];
+        n = (int)(A.segptr[r + 1] - b);
+    }
+    if (!__any(n > 0)) return;
+    const T Pr = n > 0 ? A.P[r] : T(0);
+    const uint32_t *sr = A.sr + b;
+    const double *pa = A.pa + b, *pb = A.pb + b;
+    const int32_t *pt = A.partner + b;
+
+    seg::RecordRange rr[NR];
+    int64_t cell[NR][NS];
+    bool ok[NR][NS];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int j = sub + k * G;
+        if (j < n) {
+            rr[k] = seg::record_range(sr, pa, pb, pt, j, A.ng, A.head, A.c2d, A.theta);
+        } else {
+            rr[k].first = rr[k].pf = rr[k].pc = 0;
+            rr[k].count = 0;
+            rr[k].ng = 1;
+            rr[k].base = 0;
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int s = q < rr[k].count ? seg::range_sector(rr[k], q) : -1;
+            ok[k][q] = s >= 0;
+            cell[k][q] = s >= 0 ? rr[k].base + s : 0;
+        }
+    }
+    T val[NR][NS];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int q = 0; q < NS; ++q) val[k][q] = A.f[cell[k][q]];
     SumEmit<T> se{A.f, T(0), 0};
-    for (int j = lane; j < n; j += 64)
-        seg::rebin_record(A.sr + b, A.pa + b, A.pb + b, A.partner + b, j, A.ng, A.head, A.c2d, A.theta, se);
-    const T acc = wave_sum(se.acc);
-    const int m = wave_sum(se.m);
-    if (m == 0 || !(acc > T(0))) return;
-    ScaleEmit<T> ue{A.f, T(1) + A.beta * (A.P[r] / acc - T(1))};
-    for (int j = lane; j < n; j += 64)
-        seg::rebin_record(A.sr + b, A.pa + b, A.pb + b, A.partner + b, j, A.ng, A.head, A.c2d, A.theta, ue);
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+            if (ok[k][q]) {
+                se.acc += val[k][q];
+                ++se.m;
+            }
+    // runs longer than NS, and records beyond the first NR per lane
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+        if (rr[k].count > NS) seg::emit_range(rr[k], NS, se);
+    for (int j = sub + NR * G; j < n; j += G)
+        seg::rebin_record(sr, pa, pb, pt, j, A.ng, A.head, A.c2d, A.theta, se);
+    const T acc = group_sum<T, G>(se.acc);
+    const int m = group_sum<int, G>(se.m);
+    if (n == 0 || m == 0 || !(acc > T(0))) return;
+    ScaleEmit<T> ue{A.f, T(1) + A.beta * (Pr / acc - T(1))};
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+            if (ok[k][q]) A.f[cell[k][q]] = val[k][q] * ue.g;
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+        if (rr[k].count > NS) seg::emit_range(rr[k], NS, ue);
+    for (int j = sub + NR * G; j < n; j += G)
+        seg::rebin_record(sr, pa, pb, pt, j, A.ng, A.head, A.c2d, A.theta, ue);
 }
 
 // Layout maps between the paper's numbering and the wedge-major layout.
@@ -245,6 +312,33 @@ void launch_batch_n(int nch, const BatchArgs<T, TC> &A, hipStream_t s)
 
 int pick_nch(int max_row) { return (max_row + 63) / 64; }
 
+// Arguments of batch (view v, class cl) of problem c on the wedge-major
+// image f: the class's rays, the view's projections and shift, and the
+// capped grid.
+template <class T, class TC>
+BatchArgs<T, TC> batch_args(const uspg_coeffs *c, const T *proj, T *f, double beta, int v, int cl)
+{
+    BatchArgs<T, TC> A{};
+    A.rowptr = c->rowptr.as<int64_t>();
+    A.co = c->coef.as<Coef<TC>>();
+    A.f = f;
+    A.wtot = (uint32_t)c->Wtot;
+    A.U = c->scan.det_u;
+    A.Ku = c->Ku; A.Kv = c->Kv;
+    A.beta = (T)beta;
+    A.P = proj + (int64_t)v * c->nrays;
+    A.shift = (uint32_t)(((int64_t)v * c->Wc) % c->Wtot);
+    A.cu = cl % c->Ku;
+    A.cw = cl / c->Ku;
+    A.nu = (c->scan.det_u - A.cu + c->Ku - 1) / c->Ku;
+    const int nw = (c->scan.det_v - A.cw + c->Kv - 1) / c->Kv;
+    A.ncls = A.nu * nw;
+    A.nblk = (A.ncls + kWaves - 1) / kWaves;
+    const int cap = grid_cap();
+    if (A.nblk > cap) A.nblk = cap;
+    return A;
+}
+
 // Batch-kernel timing (uspg_mart_timing).
 std::atomic<int> g_timing{0};
 std::atomic<int64_t> g_timing_launches{0};
@@ -271,17 +365,8 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
     const unsigned pb = (ncells + 255) / 256;
     hipLaunchKernelGGL(to_native<T>, dim3(pb), dim3(256), 0, s, L, image, nat);
 
-    BatchArgs<T, TC> A{};
-    A.rowptr = c->rowptr.as<int64_t>();
-    A.co = c->coef.as<Coef<TC>>();
-    A.f = nat;
-    A.wtot = (uint32_t)c->Wtot;
-    A.U = c->scan.det_u;
-    A.Ku = c->Ku; A.Kv = c->Kv;
-    A.beta = (T)beta;
     const int nch = pick_nch(c->max_row);
     const int K = c->Ku * c->Kv;
-    const int cap = grid_cap();
     int done = 0;
     const bool timing = g_timing.load() != 0 && tol == 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -294,16 +379,8 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
     for (int sw = 0; sw < n_sweeps; ++sw) {
         if (tol > 0) USPG_HIP(hipMemcpyAsync(old, nat, sizeof(T) * ncells, hipMemcpyDeviceToDevice, s));
         for (int v = 0; v < c->scan.n_views; ++v) {
-            A.P = proj + (int64_t)v * c->nrays;
-            A.shift = (uint32_t)(((int64_t)v * c->Wc) % c->Wtot);
             for (int cl = 0; cl < K; ++cl) {
-                A.cu = cl % c->Ku;
-                A.cw = cl / c->Ku;
-                A.nu = (c->scan.det_u - A.cu + c->Ku - 1) / c->Ku;
-                const int nw = (c->scan.det_v - A.cw + c->Kv - 1) / c->Kv;
-                A.ncls = A.nu * nw;
-                A.nblk = (A.ncls + kWaves - 1) / kWaves;
-                if (A.nblk > cap) A.nblk = cap;
+                const BatchArgs<T, TC> A = batch_args<T, TC>(c, proj, nat, beta, v, cl);
                 if (A.ncls == 0) continue;
                 launch_batch_n<T, TC>(nch, A, s);
                 ++launches;
@@ -365,6 +442,20 @@ int run_segments(const uspg_coeffs *c, const T *proj, T *image, void *work, int 
     A.beta = (T)beta;
     const int K = c->Ku * c->Kv;
     const unsigned pb = (ncells + 255) / 256;
+    // Lanes per ray.  Measured on the paper's scans (Tables 1 and 3): 64,
+    // except 32 when a ray's records fit two per lane on average, a class has
+    // enough rays to fill the chip at two rays per wavefront, and the image
+    // stays in cache (128^3 cone, 70 views: 20.1 us per view against 24.7).
+    // With a larger image the kernel is bound by its scattered line traffic
+    // and one ray per wavefront keeps the lines of each load together (256^3
+    // frog geometry: 67.6 against 75.8 us); with few rays per class it is
+    // bound by the latency of one ray (Cu-lump geometry, 3 x 3 lattice:
+    // 10.4 against 16.9 us).  16 lanes per ray was slower on every scan.
+    const int64_t mean = c->nrays > 0 ? (c->nseg + c->nrays - 1) / c->nrays : 0;
+    const int64_t class_rays = c->nrays / K;
+    const bool small_image = (int64_t)ncells * (int64_t)sizeof(T) <= (int64_t(32) << 20);
+    const int G = mean <= 2 * 32 && class_rays >= 4096 && small_image ? 32 : 64;
+    const int rays_per_block = kWaves * (64 / G);
     int done = 0;
     const bool timing = g_timing.load() != 0 && tol == 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -385,9 +476,12 @@ int run_segments(const uspg_coeffs *c, const T *proj, T *image, void *work, int 
                 A.nu = (c->scan.det_u - A.cu + c->Ku - 1) / c->Ku;
                 const int nw = (c->scan.det_v - A.cw + c->Kv - 1) / c->Kv;
                 A.ncls = A.nu * nw;
-                A.nblk = (A.ncls + kWaves - 1) / kWaves;
+                A.nblk = (A.ncls + rays_per_block - 1) / rays_per_block;
                 if (A.ncls == 0) continue;
-                hipLaunchKernelGGL(mart_rebin<T>, dim3(A.nblk), dim3(kBlock), 0, s, A);
+                if (G == 32)
+                    hipLaunchKernelGGL((mart_rebin<T, 32>), dim3(A.nblk), dim3(kBlock), 0, s, A);
+                else
+                    hipLaunchKernelGGL((mart_rebin<T, 64>), dim3(A.nblk), dim3(kBlock), 0, s, A);
                 ++launches;
             }
         }
@@ -459,6 +553,32 @@ int mart_timing(int enable, double *batch_ms, int64_t *batch_launches)
     if (batch_ms) *batch_ms = (double)g_timing_ns.load() * 1e-6;
     if (batch_launches) *batch_launches = g_timing_launches.load();
     return USPG_OK;
+}
+
+int batch_grid_cap() { return grid_cap(); }
+
+int batch_step(const uspg_coeffs *c, int dtype, const void *proj, void *f, double beta, int v, int cl, hipStream_t s)
+{
+    const int nch = pick_nch(c->max_row);
+    const bool cf64 = c->scan.coeff_dtype == USPG_F64;
+    if (dtype == USPG_F64) {
+        if (cf64) {
+            const auto A = batch_args<double, double>(c, (const double *)proj, (double *)f, beta, v, cl);
+            if (A.ncls) launch_batch_n<double, double>(nch, A, s);
+        } else {
+            const auto A = batch_args<double, float>(c, (const double *)proj, (double *)f, beta, v, cl);
+            if (A.ncls) launch_batch_n<double, float>(nch, A, s);
+        }
+    } else {
+        if (cf64) {
+            const auto A = batch_args<float, double>(c, (const float *)proj, (float *)f, beta, v, cl);
+            if (A.ncls) launch_batch_n<float, double>(nch, A, s);
+        } else {
+            const auto A = batch_args<float, float>(c, (const float *)proj, (float *)f, beta, v, cl);
+            if (A.ncls) launch_batch_n<float, float>(nch, A, s);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? USPG_OK : fail(USPG_E_HIP, "batch launch failed");
 }
 
 int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work,

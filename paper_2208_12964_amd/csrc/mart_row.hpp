@@ -12,6 +12,17 @@
 namespace uspg {
 namespace row {
 
+// Workgroups are dispatched round robin over the 8 XCDs; renumber them so
+// that each XCD owns one contiguous run of the virtual workgroups 0 .. nb-1
+// (neighbouring rays touch neighbouring cells, which then share that XCD's
+// L2).  A bijection on [0, nb).
+__device__ inline int xcd_block(int b, int nb)
+{
+    int xcd = b & 7, idx = b >> 3;
+    int per = nb >> 3, rem = nb & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
 template <class T>
 __device__ inline T wave_sum(T v)
 {

@@ -231,28 +231,65 @@ struct FillSink {
     }
 };
 
-// Cells of record j of a ray's row (records sr[0..n), partner indices
-// relative to the row) in the view of angle theta: calls emit(cell) for every
-// cell the record meets that its partner does not; returns their count.
+// Sectors of record j of a ray's row (records sr[0..n), partner indices
+// relative to the row) in the view of angle theta: the record's run
+// (first, count), its partner's run (pf, pc; pc = 0 without a partner), the
+// ring's sector count and the paper index of the ring's sector 0 in the
+// record's slice.
+struct RecordRange {
+    int first, count, pf, pc, ng;
+    int64_t base;
+};
+
+USPG_HD inline RecordRange record_range(const uint32_t *sr, const double *pa, const double *pb,
+                                        const int32_t *partner, int64_t j, const int32_t *ng_of,
+                                        const int64_t *head, int64_t c2d, double theta)
+{
+    RecordRange q;
+    const int ring = ring_of(sr[j]), slice = slice_of(sr[j]);
+    q.ng = ng_of[ring];
+    q.pf = 0;
+    q.pc = 0;
+    rebin_range(q.ng, pa[j], pb[j], theta, q.first, q.count);
+    const int32_t pj = partner[j];
+    if (pj >= 0) rebin_range(q.ng, pa[pj], pb[pj], theta, q.pf, q.pc);
+    q.base = (int64_t)slice * c2d + head[ring];
+    return q;
+}
+
+// Sector number of entry q of a run, or -1 when the partner's run already
+// holds it (the cells a record meets are those its partner does not).
+USPG_HD inline int range_sector(const RecordRange &rr, int q)
+{
+    int s = rr.first + q;
+    if (s >= rr.ng) s -= rr.ng;
+    return rr.pc && in_range(s, rr.pf, rr.pc, rr.ng) ? -1 : s;
+}
+
+// Calls emit(cell) for every cell of entries q0, q0 + 1, ... of a run; returns
+// their count.
+template <class Emit>
+USPG_HD int emit_range(const RecordRange &rr, int q0, Emit &emit)
+{
+    int m = 0;
+    for (int q = q0; q < rr.count; ++q) {
+        const int s = range_sector(rr, q);
+        if (s < 0) continue;
+        emit(rr.base + s);
+        ++m;
+    }
+    return m;
+}
+
+// Cells of record j of a ray's row in the view of angle theta: calls
+// emit(cell) for every cell the record meets that its partner does not;
+// returns their count.
 template <class Emit>
 USPG_HD int rebin_record(const uint32_t *sr, const double *pa, const double *pb, const int32_t *partner, int64_t j,
                          const int32_t *ng_of, const int64_t *head, int64_t c2d, double theta, Emit &emit)
 {
-    const int ring = ring_of(sr[j]), slice = slice_of(sr[j]), ng = ng_of[ring];
-    int first, count, pf = 0, pc = 0;
-    rebin_range(ng, pa[j], pb[j], theta, first, count);
-    const int32_t pj = partner[j];
-    if (pj >= 0) rebin_range(ng, pa[pj], pb[pj], theta, pf, pc);
-    const int64_t base = (int64_t)slice * c2d + head[ring];
-    int m = 0;
-    for (int q = 0; q < count; ++q) {
-        int s = first + q;
-        if (s >= ng) s -= ng;
-        if (pc && in_range(s, pf, pc, ng)) continue;
-        emit(base + s);
-        ++m;
-    }
-    return m;
+    const RecordRange rr = record_range(sr, pa, pb, partner, j, ng_of, head, c2d, theta);
+    return emit_range(rr, 0, emit);
 }
 
 // Cells of one ray's re-binned row in a view (theta): calls emit(cell) for

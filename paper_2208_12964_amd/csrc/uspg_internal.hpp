@@ -126,6 +126,12 @@ int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t
 int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work,
                 int n_sweeps, double beta, double tol, int32_t *sweeps_done, hipStream_t s);
 int mart_timing(int enable, double *batch_ms, int64_t *batch_launches);
+// Grid cap of the single-problem batch kernel, in workgroups.
+int batch_grid_cap();
+// Batch (view v, class cl) of problem c on its device-layout image f with the
+// single-problem kernel (same bits as the lockstep kernel's step).
+int batch_step(const uspg_coeffs *c, int dtype, const void *proj, void *f, double beta, int v, int cl,
+               hipStream_t s);
 // Permute an image between the paper's numbering and the device layout
 // (to_native_layout = 1: paper -> device; 0: device -> paper).
 int layout_permute(const uspg_coeffs *c, int dtype, const void *src, void *dst, int to_native_layout,

@@ -38,6 +38,9 @@ def test_paper_scan_full_size_equals_oracle(U, name, sweeps):
     assert co.lattice == lat and co.nnz == seg.count
     f = img.cpu().numpy().astype(np.float64)
     assert np.max(np.abs(f - f_ref)) / np.max(np.abs(f_ref)) <= 1e-4
+    img64, _, _, _ = U.reconstruct(w, torch.as_tensor(P, device=dev), dtype=torch.float64, remap_nc=0)
+    f64 = img64.cpu().numpy()
+    assert np.max(np.abs(f64 - f_ref)) / np.max(np.abs(f_ref)) <= 1e-10
     # bijection remap on the paper's grid (nc = 2 Nr) and the oracle's
     cart = U.to_cartesian(g, img, 2 * w.n_rings, mode="bijection")
     cref = o.remap(f_ref, 2 * w.n_rings, mode="bijection")

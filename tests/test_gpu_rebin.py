@@ -35,6 +35,10 @@ def cases():
             phantom="ellipses", n_objects=6),
         synth.parallel("gr-par70", 31, 70, 60, 1, phantom="ellipses", n_objects=6, seed=12, sweeps=5).with_(
             sector_rule="paper", rebin=True, binary=True),
+        # most rays miss the disk: empty rows next to rows of up to 47 records
+        # in one wavefront's class
+        synth.parallel("gr-wide", 24, 50, 121, 1, phantom="ellipses", n_objects=6, seed=14, sweeps=4).with_(
+            sector_rule="paper", rebin=True, binary=True, det_half_u=3.7),
     ]
 
 

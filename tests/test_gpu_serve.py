@@ -81,6 +81,41 @@ def test_engine_staggered_admission_equals_alone(U, dtype, tol):
     eng.close()
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_engine_wide_problems_equal_alone(U, dtype):
+    """Problems whose classes fill the chip alone (256-ring serving requests,
+    43,776 rays per class) run each step with the single-problem kernel, the
+    others share the lockstep launch; every result is still bit for bit the
+    one mart_run gives alone."""
+    dev = torch.device("cuda:0")
+    ws = [synth.serve_request(11, 256, 8, 1), synth.serve_request(12, 32, 8, 3),
+          synth.serve_request(13, 256, 8, 1).with_(seed=5017)]
+    print("case wide engine", dtype, [w.name for w in ws], flush=True)
+    grids = [U.Grid.from_workload(w) for w in ws]
+    cos = [U.Coeffs.from_workload(g, w, dtype) for g, w in zip(grids, ws)]
+    projs = [synth.make_projections_torch(w, dev, dtype).reshape(-1).contiguous() for w in ws]
+    alone = []
+    for co, proj, w, g in zip(cos, projs, ws, grids):
+        img = torch.ones(g.n_cells, dtype=dtype, device=dev)
+        U.mart(co, proj, img, w.sweeps, w.beta)
+        alone.append(img)
+    eng = U.Engine(3, dtype)
+    imgs = [torch.ones(g.n_cells, dtype=dtype, device=dev) for g in grids]
+    slot_of = {eng.admit(cos[0], projs[0], imgs[0], ws[0].sweeps, ws[0].beta): 0}
+    finished = []
+    for s in eng.step(5):
+        finished.append(slot_of.pop(s))
+    for i in (1, 2):
+        slot_of[eng.admit(cos[i], projs[i], imgs[i], ws[i].sweeps, ws[i].beta)] = i
+    while slot_of:
+        for s in eng.step(7):
+            finished.append(slot_of.pop(s))
+    torch.cuda.synchronize()
+    assert sorted(finished) == [0, 1, 2]
+    for i, (a, m) in enumerate(zip(alone, imgs)):
+        assert torch.equal(a, m), ws[i].name
+
+
 def test_engine_errors(U):
     dev = torch.device("cuda:0")
     w = problems()[0]

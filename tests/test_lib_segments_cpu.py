@@ -68,6 +68,9 @@ def cases():
             geometry="fan2d", n_slices=1, height=0.0, det_v=1, sector_rule="paper"),
         synth.parallel("sc-par70", 16, 70, 30, 1, phantom="none").with_(sector_rule="paper"),
         synth.parallel("sc-dip", 4, 5, 102, 5, phantom="none").with_(sector_rule="paper"),
+        # detector much wider than the disk: most rays miss, the central ones
+        # have up to 47 records
+        synth.parallel("sc-wide", 24, 50, 121, 1, phantom="none").with_(sector_rule="paper", det_half_u=3.7),
     ]
 
 
