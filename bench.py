@@ -58,10 +58,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cone-256r-32v-hc")
-    ap.add_argument("--mode", default="single", choices=["single", "batch2d", "serve", "paper"],
+    ap.add_argument("--mode", default="single", choices=["single", "batch2d", "serve", "paper", "slabs"],
                     help="single: the 256-ring cone path (default); batch2d: 64 mixed 2D slices "
                          "one at a time vs one persistent launch; serve: the request loop; paper: the "
-                         "paper's Table 1 scans with its literal segment scheme and image quality")
+                         "paper's Table 1 scans with its literal segment scheme and image quality; "
+                         "slabs: the same solve split into z-slabs (the multi-device layout) on one GPU")
+    ap.add_argument("--slabs", type=int, default=8, help="slabs: number of z-slabs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=20, help="detector rows in the oracle sample")
     ap.add_argument("--sweeps", type=int, default=0, help="override the sweep count (profiling runs)")
@@ -370,8 +372,68 @@ def bench_paper(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_slabs(args):
+    """The single-GPU workload split into z-slabs as several devices would
+    share it (every batch: each slab's part of the ray sums, their sum, each
+    slab's correction), all run here.  Reports the emulated time against the
+    fused path, the agreement of the two images and each slab's share of
+    the nonzeros; value = ray-cell updates/s of the emulated split."""
+    import torch
+
+    import paper_2208_12964_amd as U
+    import synth
+
+    dev = torch.device("cuda:0")
+    w = synth.get(args.workload)
+    if args.sweeps:
+        w = w.with_(sweeps=args.sweeps)
+    g = U.Grid.from_workload(w)
+    co = U.Coeffs.from_workload(g, w)
+    proj = synth.make_projections_torch(w, dev, torch.float32).reshape(-1).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sl = U.Slabs(co, args.slabs)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    info = [sl.info(k) for k in range(args.slabs)]
+    work = torch.empty(sl.workspace_bytes(), dtype=torch.uint8, device=dev)
+    fwork = torch.empty(co.workspace_bytes(), dtype=torch.uint8, device=dev)
+
+    def timed(fn):
+        img = torch.ones(g.n_cells, device=dev)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn(img)
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b), img
+
+    timed(lambda im: U.mart(co, proj, im, 1, w.beta, work=fwork))
+    timed(lambda im: sl.run(proj, im, 1, w.beta, work=work))
+    t_fused, f_fused = timed(lambda im: U.mart(co, proj, im, w.sweeps, w.beta, work=fwork))
+    t_slab, f_slab = timed(lambda im: sl.run(proj, im, w.sweeps, w.beta, work=work))
+    diff = ((f_fused - f_slab).abs().max() / f_fused.abs().max()).item()
+    updates = w.n_views * co.nnz * w.sweeps
+    share = max(i["nnz"] for i in info) / co.nnz
+    rays_per_class = -(-w.det_u // co.lattice[0]) * -(-w.det_v // co.lattice[1])
+    out = {"metric": f"MART ray-cell updates/s, {args.slabs} z-slabs emulated on one GPU",
+           "value": updates / (t_slab * 1e-3), "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": t_slab, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": w.name, "slabs": args.slabs, "sweeps": w.sweeps, "views": w.n_views,
+                      "lattice": list(co.lattice)},
+           "fused_ms": t_fused, "emulated_over_fused": t_slab / t_fused,
+           "max_rel_diff_vs_fused": diff, "build_ms": build_ms,
+           "slab_nnz_share": [i["nnz"] / co.nnz for i in info],
+           "largest_share_ms_per_sweep_est": t_slab / w.sweeps * share,
+           "allreduce_bytes_per_batch": rays_per_class * 4,
+           "allreduces_per_sweep": w.n_views * co.lattice[0] * co.lattice[1]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.mode == "slabs" and args.gpus == 1:
+        return bench_slabs(args)
     if args.mode == "paper" and args.gpus == 1:
         return bench_paper(args)
     if args.mode == "batch2d" and args.gpus == 1:

@@ -332,6 +332,43 @@ int uspg_engine_info(const uspg_engine *e, int32_t *active, int64_t *global_step
  * partial solve.  The caller synchronizes `stream` before freeing buffers. */
 void uspg_engine_destroy(uspg_engine *e);
 
+/* ---- z-slab decomposition --------------------------------------------------
+ * One solve split into slabs of whole slices, as several devices would
+ * share a cone-beam volume, all run on this device.  Slab g owns the cells
+ * of slices [begin_g, begin_{g+1}), begin_g = floor(g n_slices / n_slabs),
+ * and of every reference row the entries in those slices (in row order);
+ * the view shift keeps a cell in its slice, so one copy serves every view.
+ * Each (view, class) batch of eqs. 17-18 runs as: every slab's part of each
+ * ray sum (one launch per slab); the sum of the parts in slab order (the
+ * all-reduce of a multi-device run); every slab's multiplicative correction
+ * with a_max of the whole row (one launch per slab).  One slab gives
+ * mart_run's result bit for bit; more slabs change only the association of
+ * the ray sums. */
+#define USPG_MAX_SLABS 64
+typedef struct uspg_slabs uspg_slabs;
+
+/* Builds the slab rows of c (not for SEGMENTS coefficients) with
+ * 1 <= n_slabs <= min(n_slices, USPG_MAX_SLABS), else E_ARG.  Allocates
+ * the slab rows (as much device memory as c's rows), synchronises
+ * `stream`.  c must outlive the handle. */
+int uspg_build_slabs(const uspg_coeffs *c, int32_t n_slabs, void *stream, uspg_slabs **out);
+
+/* Slices [*slice_begin, *slice_end) and reference entries of one slab
+ * (nullable outputs); E_ARG for a slab out of range. */
+int uspg_slabs_info(const uspg_slabs *s, int32_t slab, int32_t *slice_begin, int32_t *slice_end, int64_t *nnz);
+
+/* Work space of mart_run_slabs: the device-layout image plus one partial
+ * ray sum per slab and ray of the largest class. */
+size_t uspg_slabs_workspace_bytes(const uspg_slabs *s, int32_t dtype);
+
+/* MART as mart_run (same proj, image, n_sweeps, beta and stream; no
+ * stopping rule), each batch split over the slabs.  E_NOMEM when work is
+ * smaller than uspg_slabs_workspace_bytes. */
+int mart_run_slabs(const uspg_slabs *s, int32_t dtype, const void *proj, void *image, void *work,
+                   size_t work_bytes, int32_t n_sweeps, double beta, void *stream);
+
+void uspg_free_slabs(uspg_slabs *s);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char *uspg_last_error(void);
 

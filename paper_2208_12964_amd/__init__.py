@@ -87,12 +87,20 @@ def lib():
     L.uspg_engine_info.argtypes = [P, P, P]
     L.uspg_engine_destroy.argtypes = [P]
     L.uspg_engine_destroy.restype = None
+    L.uspg_build_slabs.argtypes = [P, I32, P, C.POINTER(P)]
+    L.uspg_slabs_info.argtypes = [P, I32, P, P, P]
+    L.uspg_slabs_workspace_bytes.argtypes = [P, I32]
+    L.uspg_slabs_workspace_bytes.restype = SZ
+    L.mart_run_slabs.argtypes = [P, I32, P, P, P, SZ, I32, D, P]
+    L.uspg_free_slabs.argtypes = [P]
+    L.uspg_free_slabs.restype = None
     L.uspg_last_error.restype = C.c_char_p
     for name in ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_build_coeffs",
                  "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "uspg_coeffs_view_nnz", "mart_run",
                  "uspg_to_cartesian", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
                  "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_engine_create",
-                 "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info"):
+                 "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info", "uspg_build_slabs",
+                 "uspg_slabs_info", "mart_run_slabs"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -419,13 +427,60 @@ class Engine:
             pass
 
 
+class Slabs:
+    """z-slab decomposition of one solve: ``uspg_build_slabs`` /
+    ``_slabs_info`` / ``_slabs_workspace_bytes`` / ``mart_run_slabs`` /
+    ``uspg_free_slabs``.  Keeps its coefficient set alive."""
+
+    def __init__(self, coeffs: Coeffs, n_slabs: int, stream=None):
+        self.coeffs = coeffs
+        self.n_slabs = n_slabs
+        h = C.c_void_p()
+        _check(lib().uspg_build_slabs(coeffs.handle, int(n_slabs), C.c_void_p(_stream(stream)), C.byref(h)))
+        self.handle = h
+
+    def info(self, slab: int) -> dict:
+        b, e, n = C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib().uspg_slabs_info(self.handle, int(slab), C.byref(b), C.byref(e), C.byref(n)))
+        return {"slices": (b.value, e.value), "nnz": n.value}
+
+    def workspace_bytes(self, dtype=torch.float32) -> int:
+        return lib().uspg_slabs_workspace_bytes(self.handle, DTYPE[dtype])
+
+    def run(self, proj: torch.Tensor, image: torch.Tensor, n_sweeps: int, beta: float,
+            work: torch.Tensor | None = None, stream=None):
+        """``mart_run_slabs`` in place on ``image`` (paper numbering)."""
+        for t, name in ((proj, "proj"), (image, "image")):
+            _dev_check(t, name)
+        if work is None:
+            work = torch.empty(self.workspace_bytes(image.dtype), dtype=torch.uint8, device=image.device)
+        _dev_check(work, "work")
+        _check(lib().mart_run_slabs(self.handle, DTYPE[image.dtype], C.c_void_p(proj.data_ptr()),
+                                    C.c_void_p(image.data_ptr()), C.c_void_p(work.data_ptr()),
+                                    work.numel() * work.element_size(), int(n_sweeps), float(beta),
+                                    C.c_void_p(_stream(stream))))
+        _used_on(stream, proj, image, work)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().uspg_free_slabs(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 EXPORTED = ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_free_grid",
             "uspg_build_coeffs", "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts",
             "uspg_free_coeffs", "uspg_mart_workspace_bytes", "mart_run", "uspg_to_cartesian", "uspg_coeffs_view_nnz",
             "uspg_last_error", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
             "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_free_batch",
             "uspg_engine_create", "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info",
-            "uspg_engine_destroy")
+            "uspg_engine_destroy", "uspg_build_slabs", "uspg_slabs_info", "uspg_slabs_workspace_bytes",
+            "mart_run_slabs", "uspg_free_slabs")
 
 
 def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, colour=(0, 0),
@@ -441,5 +496,5 @@ def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, co
     return image, cart, grid, coeffs
 
 
-__all__ = ["Grid", "Coeffs", "Batch", "Engine", "mart", "mart_timing", "to_cartesian", "reconstruct", "USPGError", "lib", "LIB_PATH",
+__all__ = ["Grid", "Coeffs", "Batch", "Engine", "Slabs", "mart", "mart_timing", "to_cartesian", "reconstruct", "USPGError", "lib", "LIB_PATH",
            "EXPORTED", "math"]

@@ -425,19 +425,24 @@ int engine_upload(uspg_engine *e, hipStream_t s)
 // Offsets were uploaded relative to the engine's step count at this call,
 // so the launches of one call are numbered from 0.  Step t of a problem is
 // its step e->gstep + t - offset (view-major, class-minor, as in mart_run).
+// Problems are independent, so only each problem's own steps need to stay
+// in order: the lockstep steps go first, then the steps of each wide
+// problem in one run, which keeps that problem's image in the caches
+// (two 256-ring problems alternating step by step took 10 % longer).
 template <class T, class TC, int MAXC>
 int engine_launch(uspg_engine *e, int steps, hipStream_t s)
 {
-    for (int t = 0; t < steps; ++t) {
-        if (!e->table.empty())
+    if (!e->table.empty())
+        for (int t = 0; t < steps; ++t)
             hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC>), dim3(e->grid), dim3(64 * kEngineWaves), 0, s,
                                e->d_static.as<ProblemStatic>(), e->d_dyn.as<ProblemDyn<T>>(),
                                e->d_wgbeg.as<int>(), (int)e->table.size(), t);
-        for (int id : e->wide) {
-            const uspg_engine::Slot &sl = e->slots[id];
+    for (int id : e->wide) {
+        const uspg_engine::Slot &sl = e->slots[id];
+        const int K = sl.c->Ku * sl.c->Kv;
+        for (int t = 0; t < steps; ++t) {
             const int64_t local = e->gstep + t - sl.offset;
             if (local < 0 || local >= sl.total) continue;
-            const int K = sl.c->Ku * sl.c->Kv;
             const int cl = (int)(local % K);
             const int v = (int)((local / K) % sl.c->scan.n_views);
             const int rc = batch_step(sl.c, e->dtype, sl.proj, sl.work, sl.beta, v, cl, s);
