@@ -89,8 +89,8 @@ __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
 // 1 + beta (P / Pbar - 1) (eq. 18 with a_j = a_max = 1).  The image is in the
 // paper's numbering.
 //
-// A group of G lanes (32 or 64, picked per coefficient set) takes one ray,
-// so a wavefront holds 64 / G rays;
+// A group of G lanes (32, 64 or the whole workgroup of 256, picked per
+// coefficient set) takes one ray, so a wavefront holds 64 / G rays;
 // lane l of a group takes records l, l + G, ...  The runs of a lane's first
 // kRebinNR records and up to kRebinNS of their gathered values stay in
 // registers between the gather and the scatter; what does not fit is
@@ -134,11 +134,23 @@ struct ScaleEmit {
     __device__ void operator()(int64_t cell) { f[cell] = f[cell] * g; }
 };
 
+// Sum over a ray's group of G lanes.  G <= 64: xor butterfly inside the
+// wavefront.  G = 256 (the workgroup): butterfly per wavefront, then the
+// four wavefront sums added in wavefront order through LDS (every lane gets
+// the same value; the caller's workgroup reaches the barrier as a whole).
 template <class V, int G>
-__device__ inline V group_sum(V v)
+__device__ inline V group_sum(V v, V *lds)
 {
+    constexpr int W = G < 64 ? G : 64;
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if constexpr (G > 64) {
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+        __syncthreads();
+        v = lds[0];
+#pragma unroll
+        for (int w = 1; w < G / 64; ++w) v += lds[w];
+    }
     return v;
 }
 
@@ -146,11 +158,22 @@ template <class T, int G>
 __global__ __launch_bounds__(kBlock) void mart_rebin(RebinMartArgs<T> A)
 {
 #pragma clang fp contract(off)
-    constexpr int RPW = 64 / G;
+    static_assert(G == 32 || G == 64 || G == kBlock, "lanes per ray");
     constexpr int NR = kRebinNR, NS = kRebinNS;
-    const int lane = threadIdx.x & 63;
-    const int sub = lane & (G - 1);
-    const int x = (xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6)) * RPW + lane / G;
+    __shared__ T red_acc[kWaves];
+    __shared__ int red_m[kWaves];
+    int sub, x;
+    if constexpr (G == kBlock) {
+        // one ray per workgroup (n is then uniform over the workgroup, so
+        // every lane reaches the barriers of group_sum or none does)
+        sub = threadIdx.x;
+        x = xcd_block(blockIdx.x, A.nblk);
+    } else {
+        constexpr int RPW = 64 / G;
+        const int lane = threadIdx.x & 63;
+        sub = lane & (G - 1);
+        x = (xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6)) * RPW + lane / G;
+    }
     int64_t r = 0, b = 0;
     int n = 0;
     if (x < A.ncls) {
@@ -207,8 +230,8 @@ __global__ __launch_bounds__(kBlock) void mart_rebin(RebinMartArgs<T> A)
         if (rr[k].count > NS) seg::emit_range(rr[k], NS, se);
     for (int j = sub + NR * G; j < n; j += G)
         seg::rebin_record(sr, pa, pb, pt, j, A.ng, A.head, A.c2d, A.theta, se);
-    const T acc = group_sum<T, G>(se.acc);
-    const int m = group_sum<int, G>(se.m);
+    const T acc = group_sum<T, G>(se.acc, red_acc);
+    const int m = group_sum<int, G>(se.m, red_m);
     if (n == 0 || m == 0 || !(acc > T(0))) return;
     ScaleEmit<T> ue{A.f, T(1) + A.beta * (Pr / acc - T(1))};
 #pragma unroll
@@ -442,20 +465,26 @@ int run_segments(const uspg_coeffs *c, const T *proj, T *image, void *work, int 
     A.beta = (T)beta;
     const int K = c->Ku * c->Kv;
     const unsigned pb = (ncells + 255) / 256;
-    // Lanes per ray.  Measured on the paper's scans (Tables 1 and 3): 64,
-    // except 32 when a ray's records fit two per lane on average, a class has
-    // enough rays to fill the chip at two rays per wavefront, and the image
-    // stays in cache (128^3 cone, 70 views: 20.1 us per view against 24.7).
-    // With a larger image the kernel is bound by its scattered line traffic
-    // and one ray per wavefront keeps the lines of each load together (256^3
-    // frog geometry: 67.6 against 75.8 us); with few rays per class it is
-    // bound by the latency of one ray (Cu-lump geometry, 3 x 3 lattice:
-    // 10.4 against 16.9 us).  16 lanes per ray was slower on every scan.
+    // Lanes per ray, measured on the paper's scans (Tables 1 and 3; us per
+    // launch for 32 / 64 / 256 lanes):
+    //  - 256 (one ray per workgroup) when a class has few rays and they are
+    //    long: fan scans, 101 rays of 123-490 records (1024^2: 75.2 / 44.7 /
+    //    29.2; 256^2: 17.2 at 64, 15.9 at 256); Cu-lump geometry, 1,133 rays
+    //    per class of 101 records (16.9 / 10.4 / 10.3);
+    //  - 32 when a ray's records fit two per lane on average, a class has
+    //    enough rays to fill the chip at two rays per wavefront, and the
+    //    image stays in cache: 128^3 cone (20.1 / 24.7 / 40.3);
+    //  - else 64: the 256^3 frog geometry (75.8 / 67.2 / 100.2), whose 67 MB
+    //    image makes the kernel bound by its scattered line traffic, where
+    //    one ray per wavefront keeps the lines of each load together.
+    // 16 lanes per ray was slower on every scan.
     const int64_t mean = c->nrays > 0 ? (c->nseg + c->nrays - 1) / c->nrays : 0;
     const int64_t class_rays = c->nrays / K;
     const bool small_image = (int64_t)ncells * (int64_t)sizeof(T) <= (int64_t(32) << 20);
-    const int G = mean <= 2 * 32 && class_rays >= 4096 && small_image ? 32 : 64;
-    const int rays_per_block = kWaves * (64 / G);
+    const int G = class_rays < 2048 && mean > 64                           ? kBlock
+                  : mean <= 2 * 32 && class_rays >= 4096 && small_image ? 32
+                                                                          : 64;
+    const int rays_per_block = G == kBlock ? 1 : kWaves * (64 / G);
     int done = 0;
     const bool timing = g_timing.load() != 0 && tol == 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -480,6 +509,8 @@ int run_segments(const uspg_coeffs *c, const T *proj, T *image, void *work, int 
                 if (A.ncls == 0) continue;
                 if (G == 32)
                     hipLaunchKernelGGL((mart_rebin<T, 32>), dim3(A.nblk), dim3(kBlock), 0, s, A);
+                else if (G == kBlock)
+                    hipLaunchKernelGGL((mart_rebin<T, kBlock>), dim3(A.nblk), dim3(kBlock), 0, s, A);
                 else
                     hipLaunchKernelGGL((mart_rebin<T, 64>), dim3(A.nblk), dim3(kBlock), 0, s, A);
                 ++launches;

@@ -39,6 +39,10 @@ def cases():
         # in one wavefront's class
         synth.parallel("gr-wide", 24, 50, 121, 1, phantom="ellipses", n_objects=6, seed=14, sweeps=4).with_(
             sector_rule="paper", rebin=True, binary=True, det_half_u=3.7),
+        # 30 rays of up to 155 records: one ray per workgroup of 256 lanes
+        synth.small_cone("gr-fanlong", n_rings=80, n_views=20, det=30, m=5, sweeps=3).with_(
+            geometry="fan2d", n_slices=1, height=0.0, det_v=1, sector_rule="paper", rebin=True, binary=True,
+            phantom="ellipses", n_objects=6),
     ]
 
 

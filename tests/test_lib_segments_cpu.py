@@ -71,6 +71,9 @@ def cases():
         # detector much wider than the disk: most rays miss, the central ones
         # have up to 47 records
         synth.parallel("sc-wide", 24, 50, 121, 1, phantom="none").with_(sector_rule="paper", det_half_u=3.7),
+        # few long rays (up to 155 records)
+        synth.small_cone("sc-fanlong", n_rings=80, n_views=20, det=30, m=5).with_(
+            geometry="fan2d", n_slices=1, height=0.0, det_v=1, sector_rule="paper"),
     ]
 
 
