@@ -5,6 +5,8 @@
 // through `img` (global memory or LDS), Pbar and a_max reduced across the
 // wavefront in a fixed order, then
 //   f_j <- f_j (1 + beta (P / Pbar - 1) a_j / a_max).
+// Also the largest relative change of a sweep (eq. 19), shared by the
+// stored-row and segment-record solvers.
 #pragma once
 
 #include "uspg_internal.hpp"
@@ -164,6 +166,37 @@ __device__ __forceinline__ void mart_row(Img img, uint32_t shift, uint32_t wtot,
 }
 
 
+
+// max_j |f_j - g_j| / g_j (eq. 19), values are positive so their bit
+// patterns order like unsigned integers.
+template <class T> struct Bits;
+template <> struct Bits<float> { using U = unsigned int; };
+template <> struct Bits<double> { using U = unsigned long long; };
+
+template <class T>
+__global__ __launch_bounds__(256) void max_rel_change(const T *f, const T *g, uint32_t n,
+                                                      typename Bits<T>::U *out)
+{
+    __shared__ T sh[256];
+    T m = T(0);
+    for (uint32_t x = blockIdx.x * 256u + threadIdx.x; x < n; x += gridDim.x * 256u) {
+        T d = (f[x] - g[x]) / g[x];
+        d = d < T(0) ? -d : d;
+        m = d > m ? d : m;
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x + s] > sh[threadIdx.x] ? sh[threadIdx.x + s] : sh[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        T v = sh[0];
+        typename Bits<T>::U bits;
+        __builtin_memcpy(&bits, &v, sizeof(v));
+        atomicMax(out, bits);
+    }
+}
 
 }  // namespace row
 }  // namespace uspg

@@ -126,6 +126,12 @@ int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t
 int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work,
                 int n_sweeps, double beta, double tol, int32_t *sweeps_done, hipStream_t s);
 int mart_timing(int enable, double *batch_ms, int64_t *batch_launches);
+// Whether batch timing is on, and adding a timed run of launches to it.
+bool mart_timing_on();
+void mart_timing_add(int64_t ns, int64_t launches);
+// mart_rebin.hip: mart_run for segment-record coefficients.
+int rebin_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work, int n_sweeps,
+                 double beta, double tol, int32_t *sweeps_done, hipStream_t s);
 // Grid cap of the single-problem batch kernel, in workgroups.
 int batch_grid_cap();
 // Batch (view v, class cl) of problem c on its device-layout image f with the
