@@ -349,7 +349,9 @@ typedef struct uspg_slabs uspg_slabs;
 
 /* Builds the slab rows of c (not for SEGMENTS coefficients) with
  * 1 <= n_slabs <= min(n_slices, USPG_MAX_SLABS), else E_ARG.  Allocates
- * the slab rows (as much device memory as c's rows), synchronises
+ * the slab rows (as much device memory as c's rows), per slab and colour
+ * class the list of rays with entries in the slab (4 bytes per ray and
+ * slab it reaches) and per ray the set of its slabs (8 bytes); synchronises
  * `stream`.  c must outlive the handle. */
 int uspg_build_slabs(const uspg_coeffs *c, int32_t n_slabs, void *stream, uspg_slabs **out);
 

@@ -9,13 +9,16 @@
 //   1. every slab sums a_j f_j over its part of each ray of the class
 //      (slab_partial, one launch per slab, as each device would);
 //   2. the partial sums are added over the slabs in slab order (the
-//      all-reduce of a multi-device run; here each ray's waves read all of
-//      them);
+//      all-reduce of a multi-device run; here each ray's waves read the
+//      parts of the slabs holding entries of the ray, the others being
+//      zero);
 //   3. every slab applies f_j <- f_j (1 + beta (P / Pbar - 1) a_j / a_max)
 //      to its own cells (slab_apply), with a_max of the whole row.
-// With one slab the partial sum is the fused kernel's sum, in the same lane
-// order, so the result equals mart_run bit for bit; with more slabs only the
-// association of the ray sums changes.
+// A slab's launches cover only the rays of the class with entries in the
+// slab (lists built with the slab rows).  With one slab the partial sum is
+// the fused kernel's sum, in the same lane order, so the result equals
+// mart_run bit for bit; with more slabs only the association of the ray sums
+// changes.
 #include <algorithm>
 #include <vector>
 
@@ -31,6 +34,11 @@ struct uspg_slabs {
     uspg::DevBuf rowptr;            // int64 [G][nrays + 1], relative to the slab's first entry
     uspg::DevBuf coef;              // Coef<TC> [nnz], slab-major
     uspg::DevBuf amax;              // TC [nrays]: largest coefficient of the whole row
+    // Rays of each (slab, class) whose row has entries in the slab, as
+    // class-local indices: list (g, c) is xs[lofs[g K + c] .. lofs[g K + c + 1]).
+    std::vector<int64_t> lofs;
+    uspg::DevBuf xs;                // int32
+    uspg::DevBuf mask;              // uint64 [nrays]: bit g set when the ray has entries in slab g
 };
 
 namespace uspg {
@@ -122,6 +130,9 @@ struct SlabArgs {
     const int64_t *rowptr;   // this slab's, [nrays + 1]
     const Coef<TC> *co;      // this slab's first entry
     const TC *amax;          // [nrays]
+    const unsigned long long *mask;  // [nrays]: slabs holding entries of the ray
+    const int32_t *xs;       // rays of the class with entries in this slab
+    int nx;
     const T *P;              // the view's projections
     T *f;                    // device-layout image
     T *part;                 // [G][ncls] partial ray sums of the batch
@@ -131,6 +142,10 @@ struct SlabArgs {
     T beta;
 };
 
+// Rows of up to 64 * kSlabChunks entries stay in registers between the
+// gather and the scatter; longer rows are streamed.
+constexpr int kSlabChunks = 8;
+
 __device__ inline int64_t class_ray(int x, int U, int cu, int cw, int Ku, int Kv, int nu)
 {
     const int w = cw + (x / nu) * Kv;
@@ -138,58 +153,112 @@ __device__ inline int64_t class_ray(int x, int U, int cu, int cw, int Ku, int Kv
     return (int64_t)w * U + u;
 }
 
-// Step 1: this slab's part of every ray sum of the batch (zero for an empty
-// part).  Lane l adds entries l, l + 64, ... in order, then the wavefront
-// reduces, exactly as the fused kernel does for a whole row.
+// Loads the (shifted id, coefficient) pairs of a row of 1 <= n <= 64 C
+// entries and gathers their image values: every load is issued before the
+// first wait; entries past the row repeat its last id with coefficient 0.
+template <class T, class TC, int C>
+__device__ __forceinline__ void gather_row(const SlabArgs<T, TC> &A, int64_t beg, int n, int lane, uint32_t *id,
+                                           T *av, T *fv)
+{
+    const int last = n - 1;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int j = lane + 64 * k;
+        uint32_t cid;
+        TC ca;
+        load_coef(A.co + beg + (j < n ? j : last), cid, ca);
+        const uint32_t t = cid + A.shift;
+        id[k] = t >= A.wtot ? t - A.wtot : t;
+        av[k] = (T)ca * (j < n ? T(1) : T(0));
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) fv[k] = A.f[id[k]];
+}
+
+// Step 1: this slab's part of the ray sums of the batch, for the rays with
+// entries in the slab.  Lane l adds entries l, l + 64, ... in order, then the
+// wavefront reduces, exactly as the fused kernel does for a whole row.
 template <class T, class TC>
 __global__ __launch_bounds__(kBlock) void slab_partial(SlabArgs<T, TC> A)
 {
 #pragma clang fp contract(off)
+    constexpr int C = kSlabChunks;
     const int lane = threadIdx.x & 63;
     const int total = A.nblk * kWaves;
-    for (int x = xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6); x < A.ncls; x += total) {
+    for (int i = xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6); i < A.nx; i += total) {
+        const int x = A.xs[i];
         const int64_t r = class_ray(x, A.U, A.cu, A.cw, A.Ku, A.Kv, A.nu);
         const int64_t beg = A.rowptr[r];
         const int n = (int)(A.rowptr[r + 1] - beg);
         T acc = T(0);
-        for (int j = lane; j < n; j += 64) {
-            uint32_t id;
-            TC a;
-            load_coef(A.co + beg + j, id, a);
-            uint32_t t = id + A.shift;
-            t = t >= A.wtot ? t - A.wtot : t;
-            acc = fmadd((T)a, A.f[t], acc);
+        if (n > 0 && n <= 64 * C) {
+            uint32_t id[C];
+            T av[C], fv[C];
+            gather_row<T, TC, C>(A, beg, n, lane, id, av, fv);
+#pragma unroll
+            for (int k = 0; k < C; ++k) acc = fmadd(av[k], fv[k], acc);
+        } else {
+            for (int j = lane; j < n; j += 64) {
+                uint32_t id;
+                TC a;
+                load_coef(A.co + beg + j, id, a);
+                uint32_t t = id + A.shift;
+                t = t >= A.wtot ? t - A.wtot : t;
+                acc = fmadd((T)a, A.f[t], acc);
+            }
         }
         acc = wave_sum(acc);
         if (lane == 0) A.part[(int64_t)A.g * A.ncls + x] = acc;
     }
 }
 
-// Steps 2 and 3: the sum of the slabs' partial sums (in slab order), then
-// the multiplicative correction of this slab's cells.
+// Steps 2 and 3: the sum of the partial sums of the slabs holding entries of
+// the ray, in slab order (the other slabs' parts are zero), then the
+// multiplicative correction of this slab's cells.  The row's loads and
+// gathers are issued before the partial sums are read.
 template <class T, class TC>
 __global__ __launch_bounds__(kBlock) void slab_apply(SlabArgs<T, TC> A)
 {
 #pragma clang fp contract(off)
+    constexpr int C = kSlabChunks;
     const int lane = threadIdx.x & 63;
     const int total = A.nblk * kWaves;
-    for (int x = xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6); x < A.ncls; x += total) {
+    for (int i = xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6); i < A.nx; i += total) {
+        const int x = A.xs[i];
         const int64_t r = class_ray(x, A.U, A.cu, A.cw, A.Ku, A.Kv, A.nu);
         const int64_t beg = A.rowptr[r];
         const int n = (int)(A.rowptr[r + 1] - beg);
         if (n == 0) continue;
-        T acc = A.part[x];
-        for (int h = 1; h < A.G; ++h) acc += A.part[(int64_t)h * A.ncls + x];
+        const bool in_regs = n <= 64 * C;
+        uint32_t id[C];
+        T av[C], fv[C];
+        if (in_regs) gather_row<T, TC, C>(A, beg, n, lane, id, av, fv);
+        unsigned long long m = A.mask[r];
+        T acc = T(0);
+        bool first = true;
+        while (m) {
+            const int h = __builtin_ctzll(m);
+            m &= m - 1;
+            const T p = A.part[(int64_t)h * A.ncls + x];
+            acc = first ? p : acc + p;
+            first = false;
+        }
         const T amax = (T)A.amax[r];
         if (!(acc > T(0)) || !(amax > T(0))) continue;
         const T c = A.beta * (A.P[r] / acc - T(1)) / amax;
-        for (int j = lane; j < n; j += 64) {
-            uint32_t id;
-            TC a;
-            load_coef(A.co + beg + j, id, a);
-            uint32_t t = id + A.shift;
-            t = t >= A.wtot ? t - A.wtot : t;
-            A.f[t] = A.f[t] * fmadd(c, (T)a, T(1));
+        if (in_regs) {
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+                if (lane + 64 * k < n) A.f[id[k]] = fv[k] * fmadd(c, av[k], T(1));
+        } else {
+            for (int j = lane; j < n; j += 64) {
+                uint32_t id1;
+                TC a;
+                load_coef(A.co + beg + j, id1, a);
+                uint32_t t = id1 + A.shift;
+                t = t >= A.wtot ? t - A.wtot : t;
+                A.f[t] = A.f[t] * fmadd(c, (T)a, T(1));
+            }
         }
     }
 }
@@ -239,6 +308,32 @@ int build_rows(uspg_slabs *S, const int32_t *d_slab_of_slice, DevBuf &cnt, DevBu
     if (nrays > 0)
         hipLaunchKernelGGL(row_amax<TC>, dim3(rblocks), dim3(kBlock), 0, s, rp, co, nrays, S->amax.as<TC>());
     USPG_HIP(hipGetLastError());
+    // per (slab, class): the rays with entries in the slab; per ray: its slabs
+    std::vector<uint32_t> h_cnt((size_t)G * nrays);
+    USPG_HIP(hipMemcpyAsync(h_cnt.data(), cnt.p, sizeof(uint32_t) * h_cnt.size(), hipMemcpyDeviceToHost, s));
+    USPG_HIP(hipStreamSynchronize(s));
+    const int K = c->Ku * c->Kv, U = c->scan.det_u, V = c->scan.det_v;
+    std::vector<unsigned long long> h_mask(nrays, 0ull);
+    for (int g = 0; g < G; ++g)
+        for (int64_t r = 0; r < nrays; ++r)
+            if (h_cnt[(size_t)g * nrays + r]) h_mask[r] |= 1ull << g;
+    std::vector<int32_t> h_xs;
+    S->lofs.assign((size_t)G * K + 1, 0);
+    for (int g = 0; g < G; ++g)
+        for (int cl = 0; cl < K; ++cl) {
+            const int cu = cl % c->Ku, cw = cl / c->Ku;
+            const int nu = (U - cu + c->Ku - 1) / c->Ku, nw = (V - cw + c->Kv - 1) / c->Kv;
+            for (int x = 0; x < nu * nw; ++x) {
+                const int64_t r = (int64_t)(cw + (x / nu) * c->Kv) * U + cu + (x % nu) * c->Ku;
+                if (h_cnt[(size_t)g * nrays + r]) h_xs.push_back(x);
+            }
+            S->lofs[(size_t)g * K + cl + 1] = (int64_t)h_xs.size();
+        }
+    if ((rc = S->xs.alloc(sizeof(int32_t) * std::max<size_t>(h_xs.size(), 1))) != USPG_OK) return rc;
+    if ((rc = S->mask.alloc(sizeof(unsigned long long) * (size_t)std::max<int64_t>(nrays, 1))) != USPG_OK) return rc;
+    if (!h_xs.empty())
+        USPG_HIP(hipMemcpyAsync(S->xs.p, h_xs.data(), sizeof(int32_t) * h_xs.size(), hipMemcpyHostToDevice, s));
+    USPG_HIP(hipMemcpyAsync(S->mask.p, h_mask.data(), sizeof(unsigned long long) * nrays, hipMemcpyHostToDevice, s));
     USPG_HIP(hipStreamSynchronize(s));
     return USPG_OK;
 }
@@ -269,6 +364,7 @@ int run_typed(const uspg_slabs *S, const T *proj, T *image, void *work, int n_sw
     const int cap = batch_grid_cap();
     SlabArgs<T, TC> A{};
     A.amax = S->amax.as<TC>();
+    A.mask = S->mask.as<unsigned long long>();
     A.f = nat;
     A.part = part;
     A.G = S->G;
@@ -288,19 +384,21 @@ int run_typed(const uspg_slabs *S, const T *proj, T *image, void *work, int n_sw
                 A.nu = (c->scan.det_u - A.cu + c->Ku - 1) / c->Ku;
                 A.ncls = A.nu * ((c->scan.det_v - A.cw + c->Kv - 1) / c->Kv);
                 if (A.ncls == 0) continue;
-                A.nblk = std::min((A.ncls + kWaves - 1) / kWaves, cap);
-                for (int g = 0; g < S->G; ++g) {
+                // one slab's launch covers only the class's rays with entries in it
+                auto set_slab = [&](int g) {
+                    const int64_t lo = S->lofs[(size_t)g * K + cl], hi = S->lofs[(size_t)g * K + cl + 1];
                     A.g = g;
                     A.rowptr = S->rowptr.as<int64_t>() + (int64_t)g * (nrays + 1);
                     A.co = S->coef.as<Coef<TC>>() + S->start[g];
-                    hipLaunchKernelGGL((slab_partial<T, TC>), dim3(A.nblk), dim3(kBlock), 0, s, A);
-                }
-                for (int g = 0; g < S->G; ++g) {
-                    A.g = g;
-                    A.rowptr = S->rowptr.as<int64_t>() + (int64_t)g * (nrays + 1);
-                    A.co = S->coef.as<Coef<TC>>() + S->start[g];
-                    hipLaunchKernelGGL((slab_apply<T, TC>), dim3(A.nblk), dim3(kBlock), 0, s, A);
-                }
+                    A.xs = S->xs.as<int32_t>() + lo;
+                    A.nx = (int)(hi - lo);
+                    A.nblk = std::min((A.nx + kWaves - 1) / kWaves, cap);
+                    return A.nx > 0;
+                };
+                for (int g = 0; g < S->G; ++g)
+                    if (set_slab(g)) hipLaunchKernelGGL((slab_partial<T, TC>), dim3(A.nblk), dim3(kBlock), 0, s, A);
+                for (int g = 0; g < S->G; ++g)
+                    if (set_slab(g)) hipLaunchKernelGGL((slab_apply<T, TC>), dim3(A.nblk), dim3(kBlock), 0, s, A);
             }
         }
         USPG_HIP(hipGetLastError());
@@ -393,6 +491,8 @@ void uspg_free_slabs(uspg_slabs *S)
     S->rowptr.release();
     S->coef.release();
     S->amax.release();
+    S->xs.release();
+    S->mask.release();
     delete S;
 }
 
