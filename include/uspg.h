@@ -371,6 +371,25 @@ int mart_run_slabs(const uspg_slabs *s, int32_t dtype, const void *proj, void *i
 
 void uspg_free_slabs(uspg_slabs *s);
 
+/* ---- debug checks -----------------------------------------------------------
+ * Race check of the MART order (Sec. III.D: a class batch equals its rays
+ * applied one by one only if the rays of each class share no cell): for view
+ * `view` and the lattice (ku, kv), every class c = (w mod kv) ku + (u mod ku)
+ * stamps the cells of its rows, and *collisions receives the number of hits
+ * on cells another ray of the same class had already hit (0 for a valid
+ * lattice).  Independent of the conflict map the lattice was chosen from.
+ * Stored rows only (E_ARG for SEGMENTS); E_ARG for a view or lattice out of
+ * range.  Allocates a temporary 4-byte counter per device-layout cell and
+ * synchronises `stream`. */
+int uspg_check_lattice(const uspg_coeffs *c, int32_t view, int32_t ku, int32_t kv, void *stream,
+                       int64_t *collisions);
+
+/* Counts the entries of proj (device, n_views x rays of c, dtype
+ * USPG_F32 / USPG_F64) that are NaN, infinite or negative: eq. 18 keeps the
+ * image positive only for finite, non-negative data.  Synchronises
+ * `stream`. */
+int uspg_check_projections(const uspg_coeffs *c, int32_t dtype, const void *proj, void *stream, int64_t *n_bad);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char *uspg_last_error(void);
 

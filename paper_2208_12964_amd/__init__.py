@@ -94,13 +94,15 @@ def lib():
     L.mart_run_slabs.argtypes = [P, I32, P, P, P, SZ, I32, D, P]
     L.uspg_free_slabs.argtypes = [P]
     L.uspg_free_slabs.restype = None
+    L.uspg_check_lattice.argtypes = [P, I32, I32, I32, P, P]
+    L.uspg_check_projections.argtypes = [P, I32, P, P, P]
     L.uspg_last_error.restype = C.c_char_p
     for name in ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_build_coeffs",
                  "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "uspg_coeffs_view_nnz", "mart_run",
                  "uspg_to_cartesian", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
                  "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_engine_create",
                  "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info", "uspg_build_slabs",
-                 "uspg_slabs_info", "mart_run_slabs"):
+                 "uspg_slabs_info", "mart_run_slabs", "uspg_check_lattice", "uspg_check_projections"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -222,6 +224,25 @@ class Coeffs:
 
     def workspace_bytes(self, dtype=torch.float32, tol: float = 0.0) -> int:
         return int(lib().uspg_mart_workspace_bytes(self.handle, DTYPE[dtype], tol))
+
+    def check_lattice(self, view: int, lattice=None, stream=None) -> int:
+        """``uspg_check_lattice``: hits on cells already hit by another ray of
+        the same class in `view` (0 for a valid lattice; default: the chosen one)."""
+        ku, kv = lattice if lattice is not None else self.lattice
+        n = C.c_int64()
+        _check(lib().uspg_check_lattice(self.handle, int(view), int(ku), int(kv), C.c_void_p(_stream(stream)),
+                                        C.byref(n)))
+        return n.value
+
+    def check_projections(self, proj: torch.Tensor, stream=None) -> int:
+        """``uspg_check_projections``: entries of proj that are NaN, infinite or negative."""
+        _dev_check(proj, "proj")
+        if proj.numel() < self.n_views * self.n_rays:
+            raise ValueError("proj holds fewer than n_views x n_rays values")
+        n = C.c_int64()
+        _check(lib().uspg_check_projections(self.handle, DTYPE[proj.dtype], C.c_void_p(proj.data_ptr()),
+                                            C.c_void_p(_stream(stream)), C.byref(n)))
+        return n.value
 
     def close(self):
         if getattr(self, "handle", None):
@@ -480,7 +501,7 @@ EXPORTED = ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_free_
             "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_free_batch",
             "uspg_engine_create", "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info",
             "uspg_engine_destroy", "uspg_build_slabs", "uspg_slabs_info", "uspg_slabs_workspace_bytes",
-            "mart_run_slabs", "uspg_free_slabs")
+            "mart_run_slabs", "uspg_free_slabs", "uspg_check_lattice", "uspg_check_projections")
 
 
 def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, colour=(0, 0),
