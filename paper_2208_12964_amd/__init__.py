@@ -261,6 +261,21 @@ def _dev_check(t: torch.Tensor, name: str):
         raise ValueError(f"{name} must be a contiguous device tensor")
 
 
+def _problem_check(coeffs, proj: torch.Tensor, image: torch.Tensor, dtype=None):
+    """The library reads n_views x rays projections and writes n_cells image
+    values through raw pointers: refuse tensors that are too small or of
+    another dtype than the image's before any device work."""
+    _dev_check(proj, "proj")
+    _dev_check(image, "image")
+    if image.dtype not in DTYPE or proj.dtype != image.dtype or (dtype is not None and image.dtype != dtype):
+        raise ValueError("proj and image must share dtype float32 or float64 (and the caller's dtype)")
+    if proj.numel() < coeffs.n_views * coeffs.n_rays:
+        raise ValueError(f"proj holds {proj.numel()} values, fewer than n_views x rays = "
+                         f"{coeffs.n_views * coeffs.n_rays}")
+    if image.numel() < coeffs.grid.n_cells:
+        raise ValueError(f"image holds {image.numel()} values, fewer than the grid's {coeffs.grid.n_cells} cells")
+
+
 def _used_on(stream, *tensors):
     """Tell torch's caching allocator that the library's work on `stream`
     (None: the current stream) uses these tensors, so memory freed on the
@@ -275,10 +290,7 @@ def mart(coeffs: Coeffs, proj: torch.Tensor, image: torch.Tensor, n_sweeps: int,
          tol: float = 0.0, work: torch.Tensor | None = None, stream=None) -> int:
     """Sp-MART in place on ``image`` (paper numbering): ``mart_run``.
     Returns the number of sweeps run (exact only after a stream sync when tol == 0)."""
-    _dev_check(proj, "proj")
-    _dev_check(image, "image")
-    if proj.dtype != image.dtype or image.dtype not in DTYPE:
-        raise ValueError("proj and image must share dtype float32 or float64")
+    _problem_check(coeffs, proj, image)
     need = coeffs.workspace_bytes(image.dtype, tol)
     if work is None:
         work = torch.empty(need, dtype=torch.uint8, device=image.device)
@@ -297,9 +309,13 @@ def to_cartesian(grid: Grid, image: torch.Tensor, nc: int, mode: str = "point",
                  out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """USPG -> Cartesian remap (Sec. II.B): ``uspg_to_cartesian``."""
     _dev_check(image, "image")
+    if image.dtype not in DTYPE or image.numel() < grid.n_cells:
+        raise ValueError("image must be float32 / float64 with at least the grid's cells")
     if out is None:
-        out = torch.empty((grid.n_slices, nc, nc), dtype=image.dtype, device=image.device)
+        out = torch.empty((grid.n_slices, max(nc, 0), max(nc, 0)), dtype=image.dtype, device=image.device)
     _dev_check(out, "out")
+    if out.dtype != image.dtype or out.numel() < grid.n_slices * max(nc, 0) ** 2:
+        raise ValueError("out must have the image's dtype and hold n_slices x nc x nc values")
     _check(lib().uspg_to_cartesian(grid.handle, DTYPE[image.dtype], C.c_void_p(image.data_ptr()),
                                    C.c_void_p(out.data_ptr()), nc, REMAP[mode], C.c_void_p(_stream(stream))))
     return out
@@ -348,9 +364,12 @@ class Batch:
 
     def _args(self, projs, images, works, sweeps, betas):
         n = len(self.coeffs)
-        assert len(projs) == len(images) == len(works) == n
-        for t in list(projs) + list(images) + list(works):
-            _dev_check(t, "batch buffer")
+        if not (len(projs) == len(images) == len(works) == len(sweeps) == len(betas) == n):
+            raise ValueError("one projection set, image, work buffer, sweep count and beta per problem")
+        for co, p, im in zip(self.coeffs, projs, images):
+            _problem_check(co, p, im, self.dtype)
+        for t in works:
+            _dev_check(t, "work")
         wb = (C.c_size_t * n)(*[w.numel() * w.element_size() for w in works])
         sw = (C.c_int32 * n)(*[int(x) for x in sweeps])
         be = (C.c_double * n)(*[float(x) for x in betas])
@@ -404,8 +423,7 @@ class Engine:
 
     def admit(self, coeffs: Coeffs, proj: torch.Tensor, image: torch.Tensor, n_sweeps: int, beta: float,
               work: torch.Tensor | None = None, stream=None) -> int:
-        for t, name in ((proj, "proj"), (image, "image")):
-            _dev_check(t, name)
+        _problem_check(coeffs, proj, image, self.dtype)
         if work is None:
             work = torch.empty(coeffs.workspace_bytes(self.dtype), dtype=torch.uint8, device=image.device)
         _dev_check(work, "work")
@@ -471,8 +489,7 @@ class Slabs:
     def run(self, proj: torch.Tensor, image: torch.Tensor, n_sweeps: int, beta: float,
             work: torch.Tensor | None = None, stream=None):
         """``mart_run_slabs`` in place on ``image`` (paper numbering)."""
-        for t, name in ((proj, "proj"), (image, "image")):
-            _dev_check(t, name)
+        _problem_check(self.coeffs, proj, image)
         if work is None:
             work = torch.empty(self.workspace_bytes(image.dtype), dtype=torch.uint8, device=image.device)
         _dev_check(work, "work")

@@ -1,7 +1,8 @@
 """Degenerate and edge cases of the GPU path against the FP64 oracle: zero
 sweeps, one ring, one view, one detector pixel, rays that miss the grid,
 all-zero projections, a stopping rule met after the first sweep, and the
-literal scheme on a half-turn scan with three views."""
+literal scheme on a half-turn scan with three views; maximum sizes and
+short buffers are refused."""
 import math
 import os
 
@@ -93,3 +94,50 @@ def test_literal_scheme_half_turn_three_views(U):
         sector_rule="paper", rebin=True, binary=True)
     check(U, w, rebin=True)
     check(U, w, dtype=torch.float32, tol=1e-4, rebin=True)
+
+
+def test_size_limits(U):
+    """Maximum sizes are refused before any device work: more than 2^31
+    cells, 2^31 rays, 65,536 slices for segment records, a Cartesian grid of
+    2^31 pixels, and a bijection remap off the paper's grid."""
+    with pytest.raises(U.USPGError) as e:
+        U.Grid(30000, 1, 1.0, 0.0, "multiple", 8)           # about 2.8e9 cells
+    assert e.value.code == -1
+    g3 = U.Grid(4, 4, 1.0, 2.0, "multiple", 8)
+    with pytest.raises(U.USPGError) as e:
+        U.Coeffs(g3, "cone3d", 8, 2 * math.pi, 1 << 16, 1 << 15, 1.0, 1.0, 4.0, 8.0)   # 2^31 rays
+    assert e.value.code == -1
+    g = U.Grid(4, 1, 1.0, 0.0, "multiple", 8)
+    gz = U.Grid(1, 1 << 16, 1.0, 2.0, "multiple", 4)
+    with pytest.raises(U.USPGError) as e:
+        U.Coeffs(gz, "cone3d", 4, 2 * math.pi, 4, 4, 1.0, 1.0, 4.0, 8.0, weights="segments")
+    assert e.value.code == -1
+    img = torch.ones(g.n_cells, device=dev())
+    out = torch.empty(1, device=dev())
+    with pytest.raises(U.USPGError) as e:       # 46,341^2 > 2^31 pixels (refused before any write)
+        U._check(U.lib().uspg_to_cartesian(g.handle, 0, img.data_ptr(), out.data_ptr(), 46341, 0, None))
+    assert e.value.code == -1
+    with pytest.raises(U.USPGError) as e:
+        U.to_cartesian(g, img, 2 * 4, mode="bijection")     # not the paper's sector rule
+    assert e.value.code == -1
+
+
+def test_binding_refuses_short_buffers(U):
+    """The binding checks tensor sizes and dtypes against the problem before
+    handing raw pointers to the library."""
+    w = synth.get("par2d-32r-8v")
+    g = U.Grid.from_workload(w)
+    co = U.Coeffs.from_workload(g, w)
+    proj = torch.ones(w.n_views * w.det_u, device=dev())
+    img = torch.ones(g.n_cells, device=dev())
+    for p, im in ((proj[:-1], img), (proj, img[:-1]), (proj.double(), img)):
+        with pytest.raises(ValueError):
+            U.mart(co, p, im, 1, 0.1)
+    with pytest.raises(ValueError):
+        U.to_cartesian(g, img, 16, out=torch.empty(16 * 16 - 1, device=dev()))
+    eng = U.Engine(1, torch.float64)
+    with pytest.raises(ValueError):
+        eng.admit(co, proj, img, 1, 0.1)                     # float32 buffers, float64 engine
+    eng.close()
+    with pytest.raises(ValueError):
+        U.Slabs(co, 1).run(proj[:-1], img, 1, 0.1)
