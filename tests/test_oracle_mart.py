@@ -220,6 +220,43 @@ def test_class_order_contract_non_square_detector():
     assert np.array_equal(f, f_ref)
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_rays_of_a_class_commute(seed):
+    """Rays of one class share no cell, so applying them in any order gives
+    the same image bit for bit (Sec. III.D applies rays one after another;
+    the class structure is what lets the GPU apply them together).  Replayed
+    ray by ray with every class's rays in a random order, then compared with
+    the oracle's ascending order."""
+    w = synth.small_cone("perm", n_rings=6, n_views=4, det=12, m=4, n_slices=4).with_(det_v=8)
+    o = Oracle(w)
+    csr = o.trace_view(0)
+    ku, kv = o.colour(csr)
+    assert ku * kv > 1
+    P = synth.make_projections(w)
+    rng = np.random.default_rng(seed)
+    f = np.ones(o.n_cells)
+    U, V = w.det_u, w.det_v
+    for _ in range(2):
+        for v in range(w.n_views):
+            rv = o.rotate(csr, v)
+            for c in range(ku * kv):
+                rays = [r for r in range(U * V) if ((r // U) % kv) * ku + (r % U) % ku == c]
+                for r in rng.permutation(rays):
+                    ids, a = rv.row(int(r))
+                    o.mart_ray(ids, a, P[v].ravel()[int(r)], f, 0.3)
+    f_ref = o.mart(csr, (ku, kv), P, np.ones(o.n_cells), 2, 0.3)
+    assert np.array_equal(f, f_ref)
+    # a permutation across classes is another MART order and changes the bits
+    g = np.ones(o.n_cells)
+    for _ in range(2):
+        for v in range(w.n_views):
+            rv = o.rotate(csr, v)
+            for r in rng.permutation(U * V):
+                ids, a = rv.row(int(r))
+                o.mart_ray(ids, a, P[v].ravel()[int(r)], g, 0.3)
+    assert not np.array_equal(g, f_ref)
+
+
 def _replay_tiled(o, csr, lattice, tiles, P, f, beta, sweeps):
     """The order views > tile colours > tiles > classes > rays, ray by ray."""
     w = o.w
