@@ -271,8 +271,8 @@ def bench_serve(args):
     st = srv.run(reqs, progress=report)
     srv.close()
     updates = sum(it.sweeps * it.n_views * geo[it.key][1].nnz for it in items)
-    out = {"metric": "served cone-beam reconstructions/s (Poisson 20/s, 120 s, Nr in {64,128,256}, "
-                     "p in {8,16,32}, 10-20 sweeps)",
+    out = {"metric": f"served cone-beam reconstructions/s (Poisson {args.rate:g}/s, {args.duration:g} s, "
+                     "Nr in {64,128,256}, p in {8,16,32}, 10-20 sweeps)",
            "value": st["req_per_s"], "unit": "req/s", "n_gpus": 1, "steps": st["completed"], "warmup": len(geo),
            "ms_per_step": st["wall_s"] * 1e3 / max(1, st["completed"]), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
