@@ -116,9 +116,8 @@ void uspg_free_grid(uspg_grid *g);
  * azimuth at both ends); for view v both azimuths advance by v span /
  * n_views and every sector between them (eqs. 10-16) gets coefficient 1
  * (a cell met by both passes of a line through one ring counts once).  With
- * SEGMENTS any n_views and span are accepted (no USPG_E_SHIFT), the rows of
- * every view are rebuilt on the fly during MART, the colouring is the union
- * of every view's conflicts, coeff_dtype is ignored (records are FP64), and
+ * SEGMENTS any n_views and span are accepted (no USPG_E_SHIFT), the
+ * colouring is the union of every view's conflicts, coeff_dtype is ignored (records are FP64), and
  * the handle runs through mart_run only (batches and engines reject it).
  * quarter (SEGMENTS only, else ignored): 1 traces only the rays with
  * u < ceil(det_u / 2) and w < ceil(det_v / 2) and mirrors their records to
@@ -126,6 +125,13 @@ void uspg_free_grid(uspg_grid *g);
  * k to n_slices - 1 - k; Sec. III.C); 0 traces every ray.  The two agree
  * except for segment ends exactly on a radial plane, where a mirrored
  * azimuth can round to the other side.
+ * view_rows (SEGMENTS only, else ignored): the colouring re-bins the rows of
+ * every view once; with 0 they are kept on the device as (cell, 1) pairs,
+ * 8 bytes per entry plus 8 per ray and view, when that totals at most
+ * USPG_VIEW_ROWS_MAX_BYTES, and MART then reads them as stored rows; with 1,
+ * or when they do not fit, MART re-bins each view's rows from the records
+ * on the fly (Alg. 1 steps 18-38).  Both give the same cells; the ray sums
+ * may differ in FP32 rounding.
  * coeff_dtype: storage of the coefficients (USPG_F32 or USPG_F64).
  * colour_u, colour_v: 0 = choose the smallest valid lattice; otherwise the
  * lattice is checked and USPG_E_ARG is returned if two rays of one class
@@ -141,7 +147,11 @@ typedef struct {
     int32_t coeff_dtype;
     int32_t colour_u, colour_v;
     int32_t quarter;        /* SEGMENTS only: 1 traces one detector quadrant and mirrors it */
+    int32_t view_rows;      /* SEGMENTS only: 0 keeps every view's rows when they fit, 1 re-bins per view */
 } uspg_scan_desc;
+
+/* Largest size of the kept per-view rows of SEGMENTS coefficients. */
+#define USPG_VIEW_ROWS_MAX_BYTES (8LL << 30)
 
 /* Traces every view-0 ray through the grid on the device (FP64 geometry),
  * stores the reference rows (one entry per traversed cell, duplicates merged)

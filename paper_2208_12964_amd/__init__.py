@@ -42,7 +42,7 @@ class _ScanDesc(C.Structure):
                 ("det_u", C.c_int32), ("det_v", C.c_int32), ("det_half_u", C.c_double),
                 ("det_half_v", C.c_double), ("src_axis", C.c_double), ("src_det", C.c_double),
                 ("weights", C.c_int32), ("coeff_dtype", C.c_int32), ("colour_u", C.c_int32),
-                ("colour_v", C.c_int32), ("quarter", C.c_int32)]
+                ("colour_v", C.c_int32), ("quarter", C.c_int32), ("view_rows", C.c_int32)]
 
 
 _lib = None
@@ -170,12 +170,12 @@ class Coeffs:
     def __init__(self, grid: Grid, geometry: str, n_views: int, span: float, det_u: int, det_v: int = 1,
                  det_half_u: float = 1.0, det_half_v: float = 0.0, src_axis: float = 0.0,
                  src_det: float = 0.0, weights: str = "length", coeff_dtype=torch.float32,
-                 colour=(0, 0), stream=None, quarter: bool = False):
+                 colour=(0, 0), stream=None, quarter: bool = False, view_rows: str = "keep"):
         L = lib()
         self.grid = grid
         d = _ScanDesc(GEOMETRY[geometry], n_views, span, det_u, det_v, det_half_u, det_half_v,
                       src_axis, src_det, WEIGHTS[weights], DTYPE[coeff_dtype], colour[0], colour[1],
-                      1 if quarter else 0)
+                      1 if quarter else 0, {"keep": 0, "rebin": 1}[view_rows])
         h = C.c_void_p()
         _check(L.uspg_build_coeffs(grid.handle, C.byref(d), C.c_void_p(_stream(stream)), C.byref(h)))
         self.handle = h
@@ -189,10 +189,12 @@ class Coeffs:
         self.max_row, self.device_bytes = mr.value, db.value
 
     @classmethod
-    def from_workload(cls, grid: Grid, w, coeff_dtype=torch.float32, colour=(0, 0), stream=None):
+    def from_workload(cls, grid: Grid, w, coeff_dtype=torch.float32, colour=(0, 0), stream=None,
+                      view_rows: str = "keep"):
         weights = "segments" if w.rebin else ("binary" if w.binary else "length")
         return cls(grid, w.geometry, w.n_views, w.span, w.det_u, w.det_v, w.det_half_u, w.det_half_v,
-                   w.src_axis, w.src_det, weights, coeff_dtype, colour, stream, quarter=w.quarter)
+                   w.src_axis, w.src_det, weights, coeff_dtype, colour, stream, quarter=w.quarter,
+                   view_rows=view_rows)
 
     def row(self, view: int, ray: int):
         import numpy as np
@@ -522,11 +524,11 @@ EXPORTED = ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_free_
 
 
 def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, colour=(0, 0),
-                sweeps=None, beta=None, remap_nc: int = 0):
+                sweeps=None, beta=None, remap_nc: int = 0, view_rows: str = "keep"):
     """Whole path for one workload record: grid, coefficients, MART from a
     ones image, optional Cartesian remap.  Returns (image, cart, grid, coeffs)."""
     grid = Grid.from_workload(w)
-    coeffs = Coeffs.from_workload(grid, w, coeff_dtype or dtype, colour)
+    coeffs = Coeffs.from_workload(grid, w, coeff_dtype or dtype, colour, view_rows=view_rows)
     image = torch.ones(grid.n_cells, dtype=dtype, device=proj.device)
     mart(coeffs, proj.to(dtype).contiguous(), image, w.sweeps if sweeps is None else sweeps,
          w.beta if beta is None else beta)

@@ -189,6 +189,7 @@ int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *sc, void *stream
     if (sc->weights == USPG_WEIGHTS_SEGMENTS) {
         // the paper's literal scheme: any number of views, rows re-binned per view
         if (g->nr >= (1 << 16) || g->nz >= (1 << 16)) return fail(USPG_E_ARG, "segment records need < 65536 rings and slices");
+        if (sc->view_rows != 0 && sc->view_rows != 1) return fail(USPG_E_ARG, "view_rows must be 0 or 1");
         auto *c = new uspg_coeffs();
         c->g = g;
         c->scan = *sc;
@@ -202,7 +203,7 @@ int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *sc, void *stream
         c->nnz = c->nseg;
         c->max_row = c->max_seg;
         c->device_bytes = (int64_t)(c->segptr.bytes + c->seg_sr.bytes + c->seg_pa.bytes + c->seg_pb.bytes +
-                                    c->seg_partner.bytes);
+                                    c->seg_partner.bytes + c->view_rowptr.bytes + c->view_coef.bytes);
         *out = c;
         return USPG_OK;
     }
@@ -348,6 +349,8 @@ void uspg_free_coeffs(uspg_coeffs *c)
     c->seg_pa.release();
     c->seg_pb.release();
     c->seg_partner.release();
+    c->view_rowptr.release();
+    c->view_coef.release();
     delete c;
 }
 

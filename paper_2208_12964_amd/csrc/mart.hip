@@ -13,6 +13,7 @@
 //   c = beta (P / Pbar - 1) / a_max,  f_j <- f_j (1 + c a_j)   (eq. 18).
 // Rows up to 64 * 16 coefficients stay in registers between the gather and
 // the scatter; longer rows are re-read in a second pass.
+#include <algorithm>
 #include <atomic>
 
 #include "mart_row.hpp"
@@ -292,6 +293,43 @@ int mart_timing(int enable, double *batch_ms, int64_t *batch_launches)
     if (batch_ms) *batch_ms = (double)g_timing_ns.load() * 1e-6;
     if (batch_launches) *batch_launches = g_timing_launches.load();
     return USPG_OK;
+}
+
+int rows_batch_launch(const uspg_coeffs *c, int dtype, const void *proj_view, void *f, const int64_t *rowptr,
+                      const void *coef, uint32_t shift, uint32_t wtot, int cl, double beta, int max_row,
+                      hipStream_t s)
+{
+    const int nch = pick_nch(max_row);
+    auto fill = [&](auto &A) {
+        A.rowptr = rowptr;
+        A.co = static_cast<const Coef<float> *>(coef);
+        A.wtot = wtot;
+        A.shift = shift;
+        A.U = c->scan.det_u;
+        A.Ku = c->Ku;
+        A.Kv = c->Kv;
+        A.cu = cl % c->Ku;
+        A.cw = cl / c->Ku;
+        A.nu = (c->scan.det_u - A.cu + c->Ku - 1) / c->Ku;
+        A.ncls = A.nu * ((c->scan.det_v - A.cw + c->Kv - 1) / c->Kv);
+        A.nblk = std::min((A.ncls + kWaves - 1) / kWaves, grid_cap());
+    };
+    if (dtype == USPG_F64) {
+        BatchArgs<double, float> A{};
+        fill(A);
+        A.P = static_cast<const double *>(proj_view);
+        A.f = static_cast<double *>(f);
+        A.beta = beta;
+        if (A.ncls) launch_batch_n<double, float>(nch, A, s);
+    } else {
+        BatchArgs<float, float> A{};
+        fill(A);
+        A.P = static_cast<const float *>(proj_view);
+        A.f = static_cast<float *>(f);
+        A.beta = (float)beta;
+        if (A.ncls) launch_batch_n<float, float>(nch, A, s);
+    }
+    return hipGetLastError() == hipSuccess ? USPG_OK : fail(USPG_E_HIP, "batch launch failed");
 }
 
 int batch_grid_cap() { return grid_cap(); }

@@ -237,11 +237,25 @@ int run_segments(const uspg_coeffs *c, const T *proj, T *image, void *work, int 
         USPG_HIP(hipEventCreate(&ev1));
         USPG_HIP(hipEventRecord(ev0, s));
     }
+    const bool kept = c->view_coef.p != nullptr;
     for (int sw = 0; sw < n_sweeps; ++sw) {
         if (tol > 0) USPG_HIP(hipMemcpyAsync(old, f, sizeof(T) * ncells, hipMemcpyDeviceToDevice, s));
         for (int v = 0; v < c->scan.n_views; ++v) {
             A.P = proj + (int64_t)v * c->nrays;
             A.theta = seg::view_angle(v, c->scan.span, c->scan.n_views);
+            if (kept) {
+                // the view's re-binned rows, kept as (cell, 1) pairs: the
+                // stored-row kernel with no shift (eq. 18 with a_j = a_max = 1)
+                const int64_t *rp = c->view_rowptr.as<int64_t>() + (int64_t)v * (c->nrays + 1);
+                const Coef<float> *co = c->view_coef.as<Coef<float>>() + c->view_start[v];
+                for (int cl = 0; cl < K; ++cl) {
+                    const int rc = rows_batch_launch(c, sizeof(T) == sizeof(double) ? USPG_F64 : USPG_F32, A.P, f,
+                                                     rp, co, 0u, ncells, cl, beta, c->view_max_row, s);
+                    if (rc != USPG_OK) return rc;
+                    ++launches;
+                }
+                continue;
+            }
             for (int cl = 0; cl < K; ++cl) {
                 A.cu = cl % c->Ku;
                 A.cw = cl / c->Ku;

@@ -269,55 +269,86 @@ int segments_reference_view(uspg_coeffs *c, hipStream_t s)
     return rc;
 }
 
+// (cell, 1) pairs of a re-binned row set, for MART on kept rows.
+__global__ __launch_bounds__(256) void ids_to_pairs(const uint32_t *ids, int64_t n, Coef<float> *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Coef<float> e;
+    e.id = ids[i];
+    e.a = 1.0f;
+    out[i] = e;
+}
+
+// Re-bins the rows of every view (counts first, for all views), ORs every
+// view's conflicts into the mark map and chooses the lattice; with
+// view_rows == 0 keeps the rows as (cell, 1) pairs when they fit.
 int colour_segments(uspg_coeffs *c, hipStream_t s)
 {
-    const int U = c->scan.det_u, V = c->scan.det_v;
+    const int U = c->scan.det_u, V = c->scan.det_v, p = c->scan.n_views;
     const int64_t nrays = c->nrays;
     const unsigned wblocks = (unsigned)((nrays * 64 + 255) / 256);   // one wavefront per ray
     c->mark.assign((size_t)U * V, 0);
-    c->view_nnz.clear();
+    c->view_nnz.assign(p, 0);
     uint32_t *cnt = nullptr, *ids = nullptr;
-    int64_t *rowptr = nullptr;
     uint8_t *mark = nullptr;
-    int64_t cap = 0;
     int rc = USPG_OK;
     do {
         if (hipMalloc((void **)&cnt, sizeof(uint32_t) * (nrays + 1)) != hipSuccess ||
-            hipMalloc((void **)&rowptr, sizeof(int64_t) * (nrays + 1)) != hipSuccess ||
             hipMalloc((void **)&mark, (size_t)U * V) != hipSuccess) {
             rc = fail(USPG_E_NOMEM, "segment colouring: allocation failed");
             break;
         }
+        if ((rc = c->view_rowptr.alloc(sizeof(int64_t) * (size_t)p * (nrays + 1))) != USPG_OK) break;
+        int64_t *vrp = c->view_rowptr.as<int64_t>();
         if (hipMemsetAsync(mark, 0, (size_t)U * V, s) != hipSuccess) { rc = fail(USPG_E_HIP, "memset"); break; }
-        for (int v = 0; v < c->scan.n_views && rc == USPG_OK; ++v) {
-            const RebinArgs A = rebin_args(c, v);
-            hipLaunchKernelGGL(rebin_count, dim3(wblocks), dim3(256), 0, s, A, cnt);
-            if ((rc = exclusive_scan_u32_to_i64(cnt, rowptr, nrays, s)) != USPG_OK) break;
-            int64_t nnz = 0;
-            if (hipMemcpyAsync(&nnz, rowptr + nrays, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess) {
-                rc = fail(USPG_E_HIP, "segment colouring: reading the row count failed");
-                break;
-            }
-            c->view_nnz.push_back(nnz);
-            if (nnz > cap) {
-                (void)hipFree(ids);
-                ids = nullptr;
-                cap = std::max<int64_t>(nnz, 1);
-                if (hipMalloc((void **)&ids, sizeof(uint32_t) * cap) != hipSuccess) {
-                    rc = fail(USPG_E_NOMEM, "segment colouring: allocation failed");
-                    break;
-                }
-            }
-            hipLaunchKernelGGL(rebin_fill, dim3(wblocks), dim3(256), 0, s, A, rowptr, ids);
+        for (int v = 0; v < p && rc == USPG_OK; ++v) {
+            hipLaunchKernelGGL(rebin_count, dim3(wblocks), dim3(256), 0, s, rebin_args(c, v), cnt);
+            rc = exclusive_scan_u32_to_i64(cnt, vrp + (int64_t)v * (nrays + 1), nrays, s);
+        }
+        if (rc != USPG_OK) break;
+        std::vector<int64_t> h_rp((size_t)p * (nrays + 1));
+        if (hipMemcpyAsync(h_rp.data(), vrp, sizeof(int64_t) * h_rp.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = fail(USPG_E_HIP, "segment colouring: reading the row counts failed");
+            break;
+        }
+        int64_t total = 0, longest = 0, widest = 1;
+        c->view_start.assign(p + 1, 0);
+        for (int v = 0; v < p; ++v) {
+            const int64_t *rp = h_rp.data() + (size_t)v * (nrays + 1);
+            c->view_nnz[v] = rp[nrays];
+            widest = std::max<int64_t>(widest, rp[nrays]);
+            for (int64_t r = 0; r < nrays; ++r) longest = std::max<int64_t>(longest, rp[r + 1] - rp[r]);
+            total += rp[nrays];
+            c->view_start[v + 1] = total;
+        }
+        const bool keep = c->scan.view_rows == 0 &&
+                          total * (int64_t)sizeof(Coef<float>) + (int64_t)c->view_rowptr.bytes <= USPG_VIEW_ROWS_MAX_BYTES;
+        if (keep && (rc = c->view_coef.alloc(sizeof(Coef<float>) * (size_t)std::max<int64_t>(total, 1))) != USPG_OK)
+            break;
+        c->view_max_row = (int32_t)longest;
+        if (hipMalloc((void **)&ids, sizeof(uint32_t) * (size_t)widest) != hipSuccess) {
+            rc = fail(USPG_E_NOMEM, "segment colouring: allocation failed");
+            break;
+        }
+        for (int v = 0; v < p && rc == USPG_OK; ++v) {
+            const int64_t nnz = c->view_nnz[v];
+            const int64_t *rowptr = vrp + (int64_t)v * (nrays + 1);
+            hipLaunchKernelGGL(rebin_fill, dim3(wblocks), dim3(256), 0, s, rebin_args(c, v), rowptr, ids);
             if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "rebin launch failed"); break; }
+            if (keep && nnz > 0)
+                hipLaunchKernelGGL(ids_to_pairs, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, ids, nnz,
+                                   c->view_coef.as<Coef<float>>() + c->view_start[v]);
             rc = conflict_marks(rowptr, ids, 1, nrays, nnz, c->g->ncells, U, mark, s);
         }
         if (rc != USPG_OK) break;
         if (hipMemcpy(c->mark.data(), mark, (size_t)U * V, hipMemcpyDeviceToHost) != hipSuccess)
             rc = fail(USPG_E_HIP, "segment colouring: copy failed");
+        if (!keep) c->view_rowptr.release();
     } while (0);
-    (void)hipFree(cnt); (void)hipFree(ids); (void)hipFree(rowptr); (void)hipFree(mark);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(cnt); (void)hipFree(ids); (void)hipFree(mark);
     if (rc != USPG_OK) return rc;
     return choose_lattice(c);
 }

@@ -97,6 +97,13 @@ struct uspg_coeffs {
     uspg::DevBuf seg_pa, seg_pb;  // double [nseg]: reference azimuths of the two ends
     uspg::DevBuf seg_partner;     // int32 [nseg]: earlier record of the ray in the same ring and slice, -1
     std::vector<int64_t> view_nnz;  // re-binned entries of every view's rows
+    // Kept re-binned rows (view_rows == 0 and small enough): per view v the
+    // rows rowptr view_rowptr[v (nrays + 1) ...] (relative to the view's first
+    // entry view_start[v]) of (paper cell, 1) pairs in view_coef.
+    uspg::DevBuf view_rowptr;     // int64 [n_views][nrays + 1]
+    uspg::DevBuf view_coef;       // Coef<float> [sum of view_nnz]
+    std::vector<int64_t> view_start;
+    int32_t view_max_row = 0;
 };
 
 namespace uspg {
@@ -129,6 +136,12 @@ int mart_timing(int enable, double *batch_ms, int64_t *batch_launches);
 // Whether batch timing is on, and adding a timed run of launches to it.
 bool mart_timing_on();
 void mart_timing_add(int64_t ns, int64_t launches);
+// One (view, class) batch of the single-problem kernel over explicit rows
+// of (id, coefficient) pairs of float coefficients (shift added mod wtot);
+// nch bounds the register path from the longest row.
+int rows_batch_launch(const uspg_coeffs *c, int dtype, const void *proj_view, void *f, const int64_t *rowptr,
+                      const void *coef, uint32_t shift, uint32_t wtot, int cl, double beta, int max_row,
+                      hipStream_t s);
 // mart_rebin.hip: mart_run for segment-record coefficients.
 int rebin_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work, int n_sweeps,
                  double beta, double tol, int32_t *sweeps_done, hipStream_t s);

@@ -24,22 +24,24 @@ def U():
     return U
 
 
+@pytest.mark.parametrize("view_rows", ["keep", "rebin"])
 @pytest.mark.parametrize("name,sweeps", [("paper-fan-256-50v", 10), ("paper-fan-1024-50v", 4),
                                          ("paper-cone-128-70v", 2)])
-def test_paper_scan_full_size_equals_oracle(U, name, sweeps):
+def test_paper_scan_full_size_equals_oracle(U, name, sweeps, view_rows):
     from paper_2208_12964_amd.quality import report
 
     dev = torch.device("cuda:0")
     w = synth.get(name).with_(sweeps=sweeps)
-    print(f"case {name} sweeps {sweeps}", flush=True)
+    print(f"case {name} sweeps {sweeps} view rows {view_rows}", flush=True)
     P = synth.make_projections(w)
-    img, cart, g, co = U.reconstruct(w, torch.as_tensor(P, device=dev), remap_nc=0)
+    img, cart, g, co = U.reconstruct(w, torch.as_tensor(P, device=dev), remap_nc=0, view_rows=view_rows)
     o = Oracle(w, nthreads=NTHREADS)
     f_ref, seg, lat = o.reconstruct_rebin(P)
     assert co.lattice == lat and co.nnz == seg.count
     f = img.cpu().numpy().astype(np.float64)
     assert np.max(np.abs(f - f_ref)) / np.max(np.abs(f_ref)) <= 1e-4
-    img64, _, _, _ = U.reconstruct(w, torch.as_tensor(P, device=dev), dtype=torch.float64, remap_nc=0)
+    img64, _, _, _ = U.reconstruct(w, torch.as_tensor(P, device=dev), dtype=torch.float64, remap_nc=0,
+                                   view_rows=view_rows)
     f64 = img64.cpu().numpy()
     assert np.max(np.abs(f64 - f_ref)) / np.max(np.abs(f_ref)) <= 1e-10
     # bijection remap on the paper's grid (nc = 2 Nr) and the oracle's
@@ -59,7 +61,7 @@ def test_paper_scan_full_size_equals_oracle(U, name, sweeps):
     # RMSE can rise between early sweeps - the 1024^2 fan scan's RMSE after
     # 4 sweeps is above the one after 1, the 128^3 cone scan's MAE after 2
     # sweeps is above the one after 1 by 4e-5 relative - while SSIM rises)
-    img1, _, _, _ = U.reconstruct(w, torch.as_tensor(P, device=dev), sweeps=1)
+    img1, _, _, _ = U.reconstruct(w, torch.as_tensor(P, device=dev), sweeps=1, view_rows=view_rows)
     q1 = report(w, U.to_cartesian(g, img1, nc))
     assert q["ssim"] > q1["ssim"], (q, q1)
 

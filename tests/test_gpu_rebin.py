@@ -68,12 +68,15 @@ def test_rows_conflicts_lattice_equal_oracle(U, w):
             assert np.all(lens == 1.0)
 
 
+@pytest.mark.parametrize("view_rows", ["keep", "rebin"])
 @pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-10)])
 @pytest.mark.parametrize("w", cases(), ids=lambda w: w.name)
-def test_mart_equals_oracle(U, w, dtype, tol):
+def test_mart_equals_oracle(U, w, dtype, tol, view_rows):
+    """Both solvers: every view's rows kept from the colouring pass, and
+    rows re-binned from the records on the fly during MART."""
     dev = torch.device("cuda:0")
     P = synth.make_projections(w)
-    img, _, g, co = U.reconstruct(w, torch.as_tensor(P, device=dev), dtype=dtype)
+    img, _, g, co = U.reconstruct(w, torch.as_tensor(P, device=dev), dtype=dtype, view_rows=view_rows)
     f_ref, _, lat = Oracle(w, nthreads=NTHREADS).reconstruct_rebin(P)
     assert co.lattice == lat
     assert rel_err(img.cpu().numpy().astype(np.float64), f_ref) <= tol
