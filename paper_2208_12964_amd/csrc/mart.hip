@@ -11,8 +11,9 @@
 //   load ids / coefficients (coalesced), rotate ids, gather f,
 //   Pbar = sum a f and a_max by wavefront reductions (fixed order),
 //   c = beta (P / Pbar - 1) / a_max,  f_j <- f_j (1 + c a_j)   (eq. 18).
-// Rows up to 64 * 16 coefficients stay in registers between the gather and
-// the scatter; longer rows are re-read in a second pass.
+// Rows up to 64 * 16 coefficients (64 * 32 for coefficient sets whose
+// longest row needs it) stay in registers between the gather and the
+// scatter; longer rows are re-read in a second pass.
 #include <algorithm>
 #include <atomic>
 
@@ -136,7 +137,8 @@ void launch_batch_n(int nch, const BatchArgs<T, TC> &A, hipStream_t s)
     if (nch <= 2) launch_batch<T, TC, 2>(A, s);
     else if (nch <= 4) launch_batch<T, TC, 4>(A, s);
     else if (nch <= 8) launch_batch<T, TC, 8>(A, s);
-    else launch_batch<T, TC, 16>(A, s);
+    else if (nch <= 16) launch_batch<T, TC, 16>(A, s);
+    else launch_batch<T, TC, 32>(A, s);
 }
 
 int pick_nch(int max_row) { return (max_row + 63) / 64; }

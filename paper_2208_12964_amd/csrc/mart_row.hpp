@@ -145,6 +145,14 @@ __device__ __forceinline__ void mart_row(Img img, uint32_t shift, uint32_t wtot,
                                          T P, int lane)
 {
     const int chunks = (n + 63) >> 6;   // wave-uniform
+    if constexpr (MAXC > 16) {
+        // 17 .. MAXC chunks: one register body of MAXC chunks, the entries
+        // past the row masked (same sums as the streamed loop)
+        if (chunks > 16 && chunks <= MAXC) {
+            row_in_registers<T, TC, MAXC>(img, shift, wtot, beta, co, n, P, lane);
+            return;
+        }
+    }
     if (chunks > MAXC) {
         row_streamed<T, TC>(img, shift, wtot, beta, co, n, P, lane);
         return;

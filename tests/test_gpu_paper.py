@@ -24,14 +24,20 @@ def U():
     return U
 
 
+def workload(name):
+    # the 2048^2 fan scan (1,024 rings) is not one of the paper's: its rows
+    # of up to about 4,000 cells take the streamed path of the row kernel
+    return synth.paper_fan(2048, 50) if name == "paper-fan-2048-50v" else synth.get(name)
+
+
 @pytest.mark.parametrize("view_rows", ["keep", "rebin"])
 @pytest.mark.parametrize("name,sweeps", [("paper-fan-256-50v", 10), ("paper-fan-1024-50v", 4),
-                                         ("paper-cone-128-70v", 2)])
+                                         ("paper-fan-2048-50v", 2), ("paper-cone-128-70v", 2)])
 def test_paper_scan_full_size_equals_oracle(U, name, sweeps, view_rows):
     from paper_2208_12964_amd.quality import report
 
     dev = torch.device("cuda:0")
-    w = synth.get(name).with_(sweeps=sweeps)
+    w = workload(name).with_(sweeps=sweeps)
     print(f"case {name} sweeps {sweeps} view rows {view_rows}", flush=True)
     P = synth.make_projections(w)
     img, cart, g, co = U.reconstruct(w, torch.as_tensor(P, device=dev), remap_nc=0, view_rows=view_rows)
@@ -61,6 +67,8 @@ def test_paper_scan_full_size_equals_oracle(U, name, sweeps, view_rows):
     # RMSE can rise between early sweeps - the 1024^2 fan scan's RMSE after
     # 4 sweeps is above the one after 1, the 128^3 cone scan's MAE after 2
     # sweeps is above the one after 1 by 4e-5 relative - while SSIM rises)
+    if name == "paper-fan-2048-50v":
+        return          # 5,050 rays for 4.2 M cells: no quality trend after 2 sweeps
     img1, _, _, _ = U.reconstruct(w, torch.as_tensor(P, device=dev), sweeps=1, view_rows=view_rows)
     q1 = report(w, U.to_cartesian(g, img1, nc))
     assert q["ssim"] > q1["ssim"], (q, q1)
