@@ -117,8 +117,10 @@ void uspg_free_grid(uspg_grid *g);
  * n_views and every sector between them (eqs. 10-16) gets coefficient 1
  * (a cell met by both passes of a line through one ring counts once).  With
  * SEGMENTS any n_views and span are accepted (no USPG_E_SHIFT), the
- * colouring is the union of every view's conflicts, coeff_dtype is ignored (records are FP64), and
- * the handle runs through mart_run only (batches and engines reject it).
+ * colouring is the union of every view's conflicts, coeff_dtype is ignored
+ * (records are FP64; kept view rows are float pairs, so batches and engines
+ * take them with the USPG_F32 coefficient type), and batches and engines
+ * accept the handle only with its view rows kept (E_ARG otherwise).
  * quarter (SEGMENTS only, else ignored): 1 traces only the rays with
  * u < ceil(det_u / 2) and w < ceil(det_v / 2) and mirrors their records to
  * the other rays (y -> -y maps azimuth phi to 2 pi - phi, z -> -z maps slice

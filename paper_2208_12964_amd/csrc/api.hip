@@ -203,7 +203,8 @@ int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *sc, void *stream
         c->nnz = c->nseg;
         c->max_row = c->max_seg;
         c->device_bytes = (int64_t)(c->segptr.bytes + c->seg_sr.bytes + c->seg_pa.bytes + c->seg_pb.bytes +
-                                    c->seg_partner.bytes + c->view_rowptr.bytes + c->view_coef.bytes);
+                                    c->seg_partner.bytes + c->view_rowptr.bytes + c->view_coef.bytes +
+                                    c->d_view_start.bytes);
         *out = c;
         return USPG_OK;
     }
@@ -351,6 +352,7 @@ void uspg_free_coeffs(uspg_coeffs *c)
     c->seg_partner.release();
     c->view_rowptr.release();
     c->view_coef.release();
+    c->d_view_start.release();
     delete c;
 }
 

@@ -58,10 +58,29 @@ constexpr int kMaxBatch = 96;     // problems per launch (kernel-argument space)
 struct ProblemStatic {
     const int64_t *rowptr;
     const void *coef;     // Coef<TC> pairs
+    const int64_t *view_start;  // kept per-view rows: first entry of each view; null: shifted reference rows
     int64_t nrays;
     uint32_t Wc, Wtot;
     int U, Ku, Kv, n_views, lds;
 };
+
+// Rows of view v: the reference rows with the cell ids shifted by v Wc, or
+// the view's own kept rows (no shift).
+template <class TC>
+__device__ inline void view_rows(const ProblemStatic &S, int v, const int64_t *&rp, const Coef<TC> *&co,
+                                 uint32_t &shift)
+{
+    const Coef<TC> *base = static_cast<const Coef<TC> *>(S.coef);
+    if (S.view_start) {
+        rp = S.rowptr + (int64_t)v * (S.nrays + 1);
+        co = base + S.view_start[v];
+        shift = 0u;
+    } else {
+        rp = S.rowptr;
+        co = base;
+        shift = (uint32_t)(((uint64_t)v * S.Wc) % S.Wtot);
+    }
+}
 
 template <class T>
 struct ProblemDyn {
@@ -87,7 +106,6 @@ __global__ void mart_multi(MultiArgs<T> A)
     const ProblemStatic S = A.st[A.first + blockIdx.x];
     const ProblemDyn<T> D = A.dyn[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const Coef<TC> *co = static_cast<const Coef<TC> *>(S.coef);
     if (S.lds) {
         for (uint32_t i = threadIdx.x; i < S.Wtot; i += blockDim.x) lds[i] = D.f[i];
         __syncthreads();
@@ -95,7 +113,10 @@ __global__ void mart_multi(MultiArgs<T> A)
     const int K = S.Ku * S.Kv;
     for (int sw = 0; sw < D.sweeps; ++sw) {
         for (int v = 0; v < S.n_views; ++v) {
-            const uint32_t shift = (uint32_t)(((uint64_t)v * S.Wc) % S.Wtot);
+            const int64_t *rp;
+            const Coef<TC> *co;
+            uint32_t shift;
+            view_rows<TC>(S, v, rp, co, shift);
             const T *Pv = D.P + (int64_t)v * S.nrays;
             for (int c = 0; c < K; ++c) {
                 const int cu = c % S.Ku, cw = c / S.Ku;
@@ -104,8 +125,8 @@ __global__ void mart_multi(MultiArgs<T> A)
                 const int ncls = nu * nw;
                 for (int x = wave; x < ncls; x += nwaves) {
                     const int64_t r = (int64_t)(cw + (x / nu) * S.Kv) * S.U + cu + (x % nu) * S.Ku;
-                    const int64_t beg = S.rowptr[r];
-                    const int n = (int)(S.rowptr[r + 1] - beg);
+                    const int64_t beg = rp[r];
+                    const int n = (int)(rp[r + 1] - beg);
                     if (n == 0) continue;
                     if (S.lds)
                         mart_row<T, TC, MAXC>(lds, shift, S.Wtot, D.beta, co + beg, n, Pv[r], lane);
@@ -151,12 +172,15 @@ __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, co
     const int x = (b - wgbeg[lo]) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (x >= nu * nw) return;
     const int64_t r = (int64_t)(cw + (x / nu) * S.Kv) * S.U + cu + (x % nu) * S.Ku;
-    const int64_t beg = S.rowptr[r];
-    const int len = (int)(S.rowptr[r + 1] - beg);
+    const int64_t *rp;
+    const Coef<TC> *co;
+    uint32_t shift;
+    view_rows<TC>(S, v, rp, co, shift);
+    const int64_t beg = rp[r];
+    const int len = (int)(rp[r + 1] - beg);
     if (len == 0) return;
-    const uint32_t shift = (uint32_t)(((uint64_t)v * S.Wc) % S.Wtot);
-    mart_row<T, TC, MAXC>(D.f, shift, S.Wtot, D.beta, static_cast<const Coef<TC> *>(S.coef) + beg, len,
-                          D.P[(int64_t)v * S.nrays + r], threadIdx.x & 63);
+    mart_row<T, TC, MAXC>(D.f, shift, S.Wtot, D.beta, co + beg, len, D.P[(int64_t)v * S.nrays + r],
+                          threadIdx.x & 63);
 }
 
 // The step sequence is captured once into a graph (per step count and launch
@@ -242,7 +266,7 @@ int solve_native(const uspg_batch *b, const void *const *proj, void *const *work
             A.dyn[j].offset = 0;
             A.dyn[j].beta = (T)beta[first + j];
         }
-        const bool cf64 = b->co[0]->scan.coeff_dtype == USPG_F64;
+        const bool cf64 = stored_coeff_dtype(b->co[0]) == USPG_F64;
         int rc = cf64 ? launch_maxc<T, double>(b, A, count, s) : launch_maxc<T, float>(b, A, count, s);
         if (rc != USPG_OK) return rc;
     }
@@ -268,7 +292,7 @@ int solve_lockstep(uspg_batch *b, const void *const *proj, void *const *work, co
     }
     USPG_HIP(hipMemcpyAsync(b->d_dyn.p, dyn, sizeof(ProblemDyn<T>) * b->n, hipMemcpyHostToDevice, s));
     USPG_HIP(hipEventRecord(b->dyn_copied, s));
-    const bool cf64 = b->co[0]->scan.coeff_dtype == USPG_F64;
+    const bool cf64 = stored_coeff_dtype(b->co[0]) == USPG_F64;
     return cf64 ? lockstep_maxc<T, double>(b, steps, s) : lockstep_maxc<T, float>(b, steps, s);
 }
 
@@ -286,11 +310,13 @@ int solve(uspg_batch *b, const void *const *proj, void *const *work, const int32
 ProblemStatic static_of(const uspg_coeffs *c)
 {
     ProblemStatic p;
-    p.rowptr = c->rowptr.as<int64_t>();
-    p.coef = c->coef.p;
+    const bool kept = kept_rows(c);
+    p.rowptr = kept ? c->view_rowptr.as<int64_t>() : c->rowptr.as<int64_t>();
+    p.coef = kept ? c->view_coef.p : c->coef.p;
+    p.view_start = kept ? c->d_view_start.as<int64_t>() : nullptr;
     p.nrays = c->nrays;
     p.Wc = (uint32_t)c->Wc;
-    p.Wtot = (uint32_t)c->Wtot;
+    p.Wtot = (uint32_t)solve_cells(c);
     p.U = c->scan.det_u;
     p.Ku = c->Ku;
     p.Kv = c->Kv;
@@ -318,11 +344,11 @@ int upload_static(uspg_batch *b)
         const uspg_coeffs *c = b->co[i];
         ProblemStatic &p = st[i];
         p = static_of(c);
-        const size_t need = (size_t)c->Wtot * tsz;
+        const size_t need = (size_t)solve_cells(c) * tsz;
         p.lds = b->use_lds && need <= b->lds_limit;
         b->lds_mode[i] = p.lds;
         if (p.lds) b->lds_bytes = std::max(b->lds_bytes, need);
-        maxrow = std::max(maxrow, (int)c->max_row);
+        maxrow = std::max(maxrow, (int)stored_max_row(c));
     }
     b->maxc = (maxrow + 63) / 64;
     // lockstep: enough workgroups for each problem's largest class
@@ -457,7 +483,7 @@ template <class T, class TC>
 int engine_maxc(uspg_engine *e, int steps, hipStream_t s)
 {
     int64_t longest = 0;
-    for (int id : e->table) longest = std::max<int64_t>(longest, e->slots[id].c->max_row);
+    for (int id : e->table) longest = std::max<int64_t>(longest, stored_max_row(e->slots[id].c));
     const int64_t chunks = (longest + 63) / 64;
     if (chunks <= 2) return engine_launch<T, TC, 2>(e, steps, s);
     if (chunks <= 4) return engine_launch<T, TC, 4>(e, steps, s);
@@ -482,8 +508,9 @@ int uspg_build_batch(int32_t n, const uspg_coeffs *const *coeffs, int32_t dtype,
     for (int i = 0; i < n; ++i) {
         if (!coeffs[i]) return fail(USPG_E_ARG, "null coefficients in batch");
         if (coeffs[i]->device != dev) return fail(USPG_E_ARG, "coefficients on another device");
-        if (coeffs[i]->segments) return fail(USPG_E_ARG, "segment-record coefficients run through mart_run only");
-        if (coeffs[i]->scan.coeff_dtype != coeffs[0]->scan.coeff_dtype)
+        if (coeffs[i]->segments && !kept_rows(coeffs[i]))
+            return fail(USPG_E_ARG, "segment-record coefficients join a batch only with their view rows kept");
+        if (stored_coeff_dtype(coeffs[i]) != stored_coeff_dtype(coeffs[0]))
             return fail(USPG_E_ARG, "all problems of a batch must share the coefficient type");
     }
     auto *b = new uspg_batch();
@@ -646,8 +673,9 @@ int uspg_engine_admit(uspg_engine *e, const uspg_coeffs *c, const void *proj, vo
 {
     if (!e || !c || !proj || !image || !work) return fail(USPG_E_ARG, "null argument");
     if (n_sweeps <= 0 || !(beta > 0)) return fail(USPG_E_ARG, "n_sweeps > 0 and beta > 0");
-    if (c->scan.coeff_dtype != e->coeff_dtype) return fail(USPG_E_ARG, "coefficient type differs from the engine's");
-    if (c->segments) return fail(USPG_E_ARG, "segment-record coefficients run through mart_run only");
+    if (c->segments && !kept_rows(c))
+        return fail(USPG_E_ARG, "segment-record coefficients join an engine only with their view rows kept");
+    if (stored_coeff_dtype(c) != e->coeff_dtype) return fail(USPG_E_ARG, "coefficient type differs from the engine's");
     if (work_bytes < uspg_mart_workspace_bytes(c, e->dtype, 0.0)) return fail(USPG_E_NOMEM, "work space too small");
     int rc = check_device(e->device);
     if (rc != USPG_OK) return rc;

@@ -254,6 +254,11 @@ int layout_permute(const uspg_coeffs *c, int dtype, const void *src, void *dst, 
                    hipStream_t s)
 {
     const uspg_grid *g = c->g;
+    if (c->segments) {   // segment-record solves work in the paper's numbering
+        USPG_HIP(hipMemcpyAsync(dst, src, (dtype == USPG_F64 ? sizeof(double) : sizeof(float)) * (size_t)g->ncells,
+                                hipMemcpyDeviceToDevice, s));
+        return USPG_OK;
+    }
     LayoutArgs L;
     L.ring_of_off = c->d_ring_of_off.as<int32_t>();
     L.kq = c->d_kq.as<int32_t>();
@@ -338,6 +343,13 @@ int batch_grid_cap() { return grid_cap(); }
 
 int batch_step(const uspg_coeffs *c, int dtype, const void *proj, void *f, double beta, int v, int cl, hipStream_t s)
 {
+    if (kept_rows(c)) {
+        const size_t tsz = dtype == USPG_F64 ? sizeof(double) : sizeof(float);
+        return rows_batch_launch(c, dtype, static_cast<const char *>(proj) + tsz * (size_t)v * c->nrays, f,
+                                 c->view_rowptr.as<int64_t>() + (int64_t)v * (c->nrays + 1),
+                                 c->view_coef.as<Coef<float>>() + c->view_start[v], 0u, (uint32_t)c->g->ncells, cl,
+                                 beta, c->view_max_row, s);
+    }
     const int nch = pick_nch(c->max_row);
     const bool cf64 = c->scan.coeff_dtype == USPG_F64;
     if (dtype == USPG_F64) {

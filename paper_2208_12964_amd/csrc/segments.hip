@@ -345,6 +345,12 @@ int colour_segments(uspg_coeffs *c, hipStream_t s)
         if (rc != USPG_OK) break;
         if (hipMemcpy(c->mark.data(), mark, (size_t)U * V, hipMemcpyDeviceToHost) != hipSuccess)
             rc = fail(USPG_E_HIP, "segment colouring: copy failed");
+        if (keep && rc == USPG_OK) {
+            if ((rc = c->d_view_start.alloc(sizeof(int64_t) * (p + 1))) == USPG_OK &&
+                hipMemcpy(c->d_view_start.p, c->view_start.data(), sizeof(int64_t) * (p + 1),
+                          hipMemcpyHostToDevice) != hipSuccess)
+                rc = fail(USPG_E_HIP, "segment colouring: copy failed");
+        }
         if (!keep) c->view_rowptr.release();
     } while (0);
     (void)hipStreamSynchronize(s);

@@ -103,10 +103,20 @@ struct uspg_coeffs {
     uspg::DevBuf view_rowptr;     // int64 [n_views][nrays + 1]
     uspg::DevBuf view_coef;       // Coef<float> [sum of view_nnz]
     std::vector<int64_t> view_start;
+    uspg::DevBuf d_view_start;    // int64 [n_views + 1], device copy of view_start
     int32_t view_max_row = 0;
 };
 
 namespace uspg {
+
+// Whether the rows of every view are stored (kept re-binned rows of SEGMENTS
+// coefficients) rather than the reference view shifted; the image cells the
+// solver works on (device layout for shifted rows, paper numbering for kept
+// rows); the longest stored row; and the stored coefficient type.
+inline bool kept_rows(const uspg_coeffs *c) { return c->segments && c->view_coef.p != nullptr; }
+inline int64_t solve_cells(const uspg_coeffs *c) { return c->segments ? c->g->ncells : c->Wtot; }
+inline int32_t stored_max_row(const uspg_coeffs *c) { return c->segments ? c->view_max_row : c->max_row; }
+inline int32_t stored_coeff_dtype(const uspg_coeffs *c) { return c->segments ? (int32_t)USPG_F32 : c->scan.coeff_dtype; }
 
 // Rings per group of the blocked device layout.
 constexpr int kRingGroup = 4;

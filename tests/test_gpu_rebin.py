@@ -1,8 +1,9 @@
 """The paper's literal variant on the GPU (weights = SEGMENTS): segment
 records re-binned per view for view counts that are not whole sector shifts.
 Rows, conflict map and lattice equal the FP64 oracle's; MART is within 1e-4
-(FP32) / 1e-10 (FP64) of the oracle's; the handle is refused by batches and
-engines."""
+(FP32) / 1e-10 (FP64) of the oracle's, with every view's rows kept or
+re-binned on the fly; with kept rows the problems join batches and engines
+bit for bit."""
 import os
 
 import numpy as np
@@ -125,19 +126,58 @@ def test_stopping_rule_and_resume(U):
     assert rel_err(c.cpu().numpy(), ref) <= 1e-10
 
 
-def test_segments_refused_by_batch_and_engine(U):
+def _alone(U, co, g, proj, w):
+    img = torch.ones(g.n_cells, device=proj.device)
+    U.mart(co, proj, img, w.sweeps, w.beta)
+    return img
+
+
+def test_kept_rows_join_batches_and_engines(U):
+    """Literal-scheme problems whose view rows are kept run in batches
+    (lockstep and persistent) and in the serving engine beside stored-row
+    problems, each ending bit for bit as mart_run alone; with rows re-binned
+    on the fly they are refused."""
     dev = torch.device("cuda:0")
-    w = cases()[0]
-    g = U.Grid.from_workload(w)
-    co = U.Coeffs.from_workload(g, w)
+    ws = [cases()[0], synth.parallel("b-par", 16, 8, 32, 16, phantom="ellipses", n_objects=5, seed=31, sweeps=3),
+          cases()[2], synth.small_cone("b-cone", n_rings=8, n_views=4, det=16, m=4, n_slices=5, sweeps=3)]
+    grids = [U.Grid.from_workload(w) for w in ws]
+    cos = [U.Coeffs.from_workload(g, w) for g, w in zip(grids, ws)]
+    projs = [torch.as_tensor(synth.make_projections(w), dtype=torch.float32, device=dev).reshape(-1).contiguous()
+             for w in ws]
+    alone = [_alone(U, co, g, p, w) for co, g, p, w in zip(cos, grids, projs, ws)]
+    b = U.Batch(cos)
+    for mode, lds in (("lockstep", False), ("persistent", True), ("persistent", False)):
+        b.set(mode, 256, lds)
+        imgs = [torch.ones(g.n_cells, device=dev) for g in grids]
+        b.run(projs, imgs, [w.sweeps for w in ws], [w.beta for w in ws])
+        torch.cuda.synchronize()
+        for i, (a, m) in enumerate(zip(alone, imgs)):
+            assert torch.equal(a, m), (mode, lds, ws[i].name)
+    eng = U.Engine(2)
+    imgs = [torch.ones(g.n_cells, device=dev) for g in grids]
+    todo, slot_of = list(range(len(ws))), {}
+    while todo or slot_of:
+        while todo and len(slot_of) < 2:
+            i = todo.pop(0)
+            slot_of[eng.admit(cos[i], projs[i], imgs[i], ws[i].sweeps, ws[i].beta)] = i
+        for sl in eng.step(5):
+            slot_of.pop(sl)
+    torch.cuda.synchronize()
+    for i, (a, m) in enumerate(zip(alone, imgs)):
+        assert torch.equal(a, m), ("engine", ws[i].name)
+    eng.close()
+    # the literal problems against the oracle as well
+    for i in (0, 2):
+        f_ref, _, _ = Oracle(ws[i], nthreads=NTHREADS).reconstruct_rebin(synth.make_projections(ws[i]))
+        assert rel_err(alone[i].cpu().numpy().astype(np.float64), f_ref) <= 1e-4
+    # rows re-binned on the fly: refused
+    co_r = U.Coeffs.from_workload(grids[0], ws[0], view_rows="rebin")
     with pytest.raises(U.USPGError) as e:
-        U.Batch([co])
+        U.Batch([co_r])
     assert e.value.code == -1
     eng = U.Engine(2)
-    proj = torch.zeros(w.n_views * w.det_u * w.det_v, device=dev)
-    img = torch.ones(g.n_cells, device=dev)
     with pytest.raises(U.USPGError) as e:
-        eng.admit(co, proj, img, 1, 0.1)
+        eng.admit(co_r, projs[0], torch.ones(grids[0].n_cells, device=dev), 1, 0.1)
     assert e.value.code == -1
     eng.close()
 
