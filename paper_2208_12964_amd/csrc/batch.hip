@@ -36,6 +36,7 @@ struct uspg_batch {
     size_t lds_limit = 0;         // bytes of dynamic LDS a workgroup may use
     size_t lds_bytes = 0;         // dynamic LDS of the launch
     int maxc = 16;
+    bool any_kept = false;        // some problem runs kept per-view rows
     std::vector<int> lds_mode;    // per problem
     // lockstep
     uspg::DevBuf d_dyn, d_wgbeg;  // per-problem run arguments, workgroup prefix
@@ -58,28 +59,34 @@ constexpr int kMaxBatch = 96;     // problems per launch (kernel-argument space)
 struct ProblemStatic {
     const int64_t *rowptr;
     const void *coef;     // Coef<TC> pairs
-    const int64_t *view_start;  // kept per-view rows: first entry of each view; null: shifted reference rows
     int64_t nrays;
     uint32_t Wc, Wtot;
     int U, Ku, Kv, n_views, lds;
+    const int64_t *view_start;  // kept per-view rows: first entry of each view; null: shifted reference rows
 };
 
-// Rows of view v: the reference rows with the cell ids shifted by v Wc, or
-// the view's own kept rows (no shift).
-template <class TC>
-__device__ inline void view_rows(const ProblemStatic &S, int v, const int64_t *&rp, const Coef<TC> *&co,
-                                 uint32_t &shift)
+// Rows of view v: the reference rows with the cell ids shifted by v Wc
+// (v < n_views <= q, so v Wc < Wtot), or the view's own kept rows (no
+// shift).  Row pointers first, so that an empty row costs nothing more.
+// KEPT = false: no problem of the launch has kept rows, and the kernels
+// compile without the per-problem test.
+template <bool KEPT>
+__device__ inline const int64_t *view_rowptr(const ProblemStatic &S, int v)
+{
+    if constexpr (!KEPT) return S.rowptr;
+    return S.view_start ? S.rowptr + (int64_t)v * (S.nrays + 1) : S.rowptr;
+}
+
+template <class TC, bool KEPT>
+__device__ inline const Coef<TC> *view_coef(const ProblemStatic &S, int v, uint32_t &shift)
 {
     const Coef<TC> *base = static_cast<const Coef<TC> *>(S.coef);
-    if (S.view_start) {
-        rp = S.rowptr + (int64_t)v * (S.nrays + 1);
-        co = base + S.view_start[v];
-        shift = 0u;
-    } else {
-        rp = S.rowptr;
-        co = base;
+    if constexpr (!KEPT) {
         shift = (uint32_t)(((uint64_t)v * S.Wc) % S.Wtot);
+        return base;
     }
+    shift = S.view_start ? 0u : (uint32_t)v * S.Wc;
+    return S.view_start ? base + S.view_start[v] : base;
 }
 
 template <class T>
@@ -98,7 +105,7 @@ struct MultiArgs {
     ProblemDyn<T> dyn[kMaxBatch];
 };
 
-template <class T, class TC, int MAXC>
+template <class T, class TC, int MAXC, bool KEPT>
 __global__ void mart_multi(MultiArgs<T> A)
 {
     extern __shared__ unsigned char smem[];
@@ -113,10 +120,9 @@ __global__ void mart_multi(MultiArgs<T> A)
     const int K = S.Ku * S.Kv;
     for (int sw = 0; sw < D.sweeps; ++sw) {
         for (int v = 0; v < S.n_views; ++v) {
-            const int64_t *rp;
-            const Coef<TC> *co;
+            const int64_t *rp = view_rowptr<KEPT>(S, v);
             uint32_t shift;
-            view_rows<TC>(S, v, rp, co, shift);
+            const Coef<TC> *co = view_coef<TC, KEPT>(S, v, shift);
             const T *Pv = D.P + (int64_t)v * S.nrays;
             for (int c = 0; c < K; ++c) {
                 const int cu = c % S.Ku, cw = c / S.Ku;
@@ -146,7 +152,7 @@ __global__ void mart_multi(MultiArgs<T> A)
 // prefix range holds it; its wavefronts take that problem's rays of the
 // current (view, class) in order.  (Capping this grid and striding, as the
 // single-problem batch kernel does, made it 6-42 % slower.)
-template <class T, class TC, int MAXC>
+template <class T, class TC, int MAXC, bool KEPT>
 __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, const ProblemDyn<T> *dyn,
                                                      const int *wgbeg, int n, int step)
 {
@@ -172,13 +178,12 @@ __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, co
     const int x = (b - wgbeg[lo]) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (x >= nu * nw) return;
     const int64_t r = (int64_t)(cw + (x / nu) * S.Kv) * S.U + cu + (x % nu) * S.Ku;
-    const int64_t *rp;
-    const Coef<TC> *co;
-    uint32_t shift;
-    view_rows<TC>(S, v, rp, co, shift);
+    const int64_t *rp = view_rowptr<KEPT>(S, v);
     const int64_t beg = rp[r];
     const int len = (int)(rp[r + 1] - beg);
     if (len == 0) return;
+    uint32_t shift;
+    const Coef<TC> *co = view_coef<TC, KEPT>(S, v, shift);
     mart_row<T, TC, MAXC>(D.f, shift, S.Wtot, D.beta, co + beg, len, D.P[(int64_t)v * S.nrays + r],
                           threadIdx.x & 63);
 }
@@ -186,7 +191,7 @@ __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, co
 // The step sequence is captured once into a graph (per step count and launch
 // shape) and replayed with one graph launch; the run arguments it reads live
 // in d_dyn, refreshed before every replay.
-template <class T, class TC, int MAXC>
+template <class T, class TC, int MAXC, bool KEPT>
 int lockstep_typed(uspg_batch *b, int steps, hipStream_t s)
 {
     const int grid = b->wgbeg[b->n];
@@ -202,7 +207,7 @@ int lockstep_typed(uspg_batch *b, int steps, hipStream_t s)
             rc = fail(USPG_E_HIP, "hipStreamBeginCapture failed");
         } else {
             for (int t = 0; t < steps; ++t)
-                hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC>), dim3(grid), dim3(b->block), 0, cs,
+                hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC, KEPT>), dim3(grid), dim3(b->block), 0, cs,
                                    b->d_static.as<ProblemStatic>(), b->d_dyn.as<ProblemDyn<T>>(),
                                    b->d_wgbeg.as<int>(), b->n, t);
             if (hipStreamEndCapture(cs, &b->graph) != hipSuccess ||
@@ -222,16 +227,22 @@ int lockstep_typed(uspg_batch *b, int steps, hipStream_t s)
 template <class T, class TC>
 int lockstep_maxc(uspg_batch *b, int steps, hipStream_t s)
 {
-    if (b->maxc <= 2) return lockstep_typed<T, TC, 2>(b, steps, s);
-    if (b->maxc <= 4) return lockstep_typed<T, TC, 4>(b, steps, s);
-    if (b->maxc <= 8) return lockstep_typed<T, TC, 8>(b, steps, s);
-    return lockstep_typed<T, TC, 16>(b, steps, s);
+    if (b->any_kept) {
+        if (b->maxc <= 2) return lockstep_typed<T, TC, 2, true>(b, steps, s);
+        if (b->maxc <= 4) return lockstep_typed<T, TC, 4, true>(b, steps, s);
+        if (b->maxc <= 8) return lockstep_typed<T, TC, 8, true>(b, steps, s);
+        return lockstep_typed<T, TC, 16, true>(b, steps, s);
+    }
+    if (b->maxc <= 2) return lockstep_typed<T, TC, 2, false>(b, steps, s);
+    if (b->maxc <= 4) return lockstep_typed<T, TC, 4, false>(b, steps, s);
+    if (b->maxc <= 8) return lockstep_typed<T, TC, 8, false>(b, steps, s);
+    return lockstep_typed<T, TC, 16, false>(b, steps, s);
 }
 
-template <class T, class TC, int MAXC>
+template <class T, class TC, int MAXC, bool KEPT>
 int launch_typed(const uspg_batch *b, MultiArgs<T> &A, int count, hipStream_t s)
 {
-    auto k = mart_multi<T, TC, MAXC>;
+    auto k = mart_multi<T, TC, MAXC, KEPT>;
     if (b->lds_bytes > 65536)
         USPG_HIP(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)b->lds_bytes));
@@ -243,10 +254,16 @@ int launch_typed(const uspg_batch *b, MultiArgs<T> &A, int count, hipStream_t s)
 template <class T, class TC>
 int launch_maxc(const uspg_batch *b, MultiArgs<T> &A, int count, hipStream_t s)
 {
-    if (b->maxc <= 2) return launch_typed<T, TC, 2>(b, A, count, s);
-    if (b->maxc <= 4) return launch_typed<T, TC, 4>(b, A, count, s);
-    if (b->maxc <= 8) return launch_typed<T, TC, 8>(b, A, count, s);
-    return launch_typed<T, TC, 16>(b, A, count, s);
+    if (b->any_kept) {
+        if (b->maxc <= 2) return launch_typed<T, TC, 2, true>(b, A, count, s);
+        if (b->maxc <= 4) return launch_typed<T, TC, 4, true>(b, A, count, s);
+        if (b->maxc <= 8) return launch_typed<T, TC, 8, true>(b, A, count, s);
+        return launch_typed<T, TC, 16, true>(b, A, count, s);
+    }
+    if (b->maxc <= 2) return launch_typed<T, TC, 2, false>(b, A, count, s);
+    if (b->maxc <= 4) return launch_typed<T, TC, 4, false>(b, A, count, s);
+    if (b->maxc <= 8) return launch_typed<T, TC, 8, false>(b, A, count, s);
+    return launch_typed<T, TC, 16, false>(b, A, count, s);
 }
 
 // Solve on device-layout images (already permuted into work[i]).
@@ -338,6 +355,7 @@ int upload_static(uspg_batch *b)
     const size_t tsz = b->dtype == USPG_F64 ? sizeof(double) : sizeof(float);
     std::vector<ProblemStatic> st(b->n);
     b->lds_bytes = 0;
+    b->any_kept = false;
     b->lds_mode.assign(b->n, 0);
     int maxrow = 0;
     for (int i = 0; i < b->n; ++i) {
@@ -349,6 +367,7 @@ int upload_static(uspg_batch *b)
         b->lds_mode[i] = p.lds;
         if (p.lds) b->lds_bytes = std::max(b->lds_bytes, need);
         maxrow = std::max(maxrow, (int)stored_max_row(c));
+        b->any_kept = b->any_kept || kept_rows(c);
     }
     b->maxc = (maxrow + 63) / 64;
     // lockstep: enough workgroups for each problem's largest class
@@ -455,12 +474,12 @@ int engine_upload(uspg_engine *e, hipStream_t s)
 // in order: the lockstep steps go first, then the steps of each wide
 // problem in one run, which keeps that problem's image in the caches
 // (two 256-ring problems alternating step by step took 10 % longer).
-template <class T, class TC, int MAXC>
+template <class T, class TC, int MAXC, bool KEPT>
 int engine_launch(uspg_engine *e, int steps, hipStream_t s)
 {
     if (!e->table.empty())
         for (int t = 0; t < steps; ++t)
-            hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC>), dim3(e->grid), dim3(64 * kEngineWaves), 0, s,
+            hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC, KEPT>), dim3(e->grid), dim3(64 * kEngineWaves), 0, s,
                                e->d_static.as<ProblemStatic>(), e->d_dyn.as<ProblemDyn<T>>(),
                                e->d_wgbeg.as<int>(), (int)e->table.size(), t);
     for (int id : e->wide) {
@@ -483,12 +502,22 @@ template <class T, class TC>
 int engine_maxc(uspg_engine *e, int steps, hipStream_t s)
 {
     int64_t longest = 0;
-    for (int id : e->table) longest = std::max<int64_t>(longest, stored_max_row(e->slots[id].c));
+    bool kept = false;
+    for (int id : e->table) {
+        longest = std::max<int64_t>(longest, stored_max_row(e->slots[id].c));
+        kept = kept || kept_rows(e->slots[id].c);
+    }
     const int64_t chunks = (longest + 63) / 64;
-    if (chunks <= 2) return engine_launch<T, TC, 2>(e, steps, s);
-    if (chunks <= 4) return engine_launch<T, TC, 4>(e, steps, s);
-    if (chunks <= 8) return engine_launch<T, TC, 8>(e, steps, s);
-    return engine_launch<T, TC, 16>(e, steps, s);
+    if (kept) {
+        if (chunks <= 2) return engine_launch<T, TC, 2, true>(e, steps, s);
+        if (chunks <= 4) return engine_launch<T, TC, 4, true>(e, steps, s);
+        if (chunks <= 8) return engine_launch<T, TC, 8, true>(e, steps, s);
+        return engine_launch<T, TC, 16, true>(e, steps, s);
+    }
+    if (chunks <= 2) return engine_launch<T, TC, 2, false>(e, steps, s);
+    if (chunks <= 4) return engine_launch<T, TC, 4, false>(e, steps, s);
+    if (chunks <= 8) return engine_launch<T, TC, 8, false>(e, steps, s);
+    return engine_launch<T, TC, 16, false>(e, steps, s);
 }
 
 }  // namespace
