@@ -24,8 +24,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 PROFILE = os.path.join(ROOT, "profiles", "mart_batch-cone-256r-32v-hc.md")
-# sources of the mart_batch kernel: the launch file, then the per-ray routine
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2208_12964_amd", "csrc", f) for f in ("mart.hip", "mart_row.hpp")]
+# sources of the mart_batch kernel: the kernel, then the per-ray routine
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2208_12964_amd", "csrc", f) for f in ("mart_batch.hpp", "mart_row.hpp")]
 
 
 def kernel_sha256() -> str:

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <atomic>
 
+#include "mart_batch.hpp"
 #include "mart_row.hpp"
 #include "uspg_internal.hpp"
 
@@ -30,8 +31,10 @@ using row::xcd_block;
 using row::wave_max;
 using row::wave_sum;
 
-constexpr int kWaves = 4;             // wavefronts per workgroup
-constexpr int kBlock = 64 * kWaves;
+using batchk::BatchArgs;
+using batchk::mart_batch;
+constexpr int kWaves = batchk::kWaves;
+constexpr int kBlock = batchk::kBlock;
 // Grid cap of the batch kernel, in workgroups per compute unit: measured on
 // the 256-ring cone (43,690 rays per class), 16 per CU (4,096 on 256 CUs)
 // gave 122 us per batch against 135 us for one wavefront per ray; 8, 12,
@@ -51,37 +54,6 @@ int grid_cap()
         cap[dev] = kBlocksPerCU * cus;
     }
     return cap[dev];
-}
-
-template <class T, class TC>
-struct BatchArgs {
-    const int64_t *rowptr;
-    const Coef<TC> *co;
-    const T *P;        // projections of the view, [rays]
-    T *f;              // wedge-major image
-    uint32_t shift;    // v * Wc (mod Wtot)
-    uint32_t wtot;
-    int U, cu, cw, Ku, Kv, nu, ncls, nblk;
-    T beta;
-};
-
-// The grid is capped (kBlocksPerCU workgroups per CU) and each wavefront
-// strides through the class by the grid's wavefront count; the rays of a
-// class share no cell, so the assignment changes no result.
-template <class T, class TC, int MAXC>
-__global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
-{
-    const int lane = threadIdx.x & 63;
-    const int total = A.nblk * kWaves;
-    for (int x = xcd_block(blockIdx.x, A.nblk) * kWaves + (threadIdx.x >> 6); x < A.ncls; x += total) {
-        const int w = A.cw + (x / A.nu) * A.Kv;
-        const int u = A.cu + (x % A.nu) * A.Ku;
-        const int64_t r = (int64_t)w * A.U + u;
-        const int64_t beg = A.rowptr[r];
-        const int n = (int)(A.rowptr[r + 1] - beg);
-        if (n == 0) continue;
-        mart_row<T, TC, MAXC>(A.f, A.shift, A.wtot, A.beta, A.co + beg, n, A.P[r], lane);
-    }
 }
 
 // Layout maps between the paper's numbering and the wedge-major layout.
