@@ -457,8 +457,9 @@ def main():
     if args.mode == "serve" and args.gpus == 1:
         return bench_serve(args)
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(independent reconstructions shard with no communication; see the design notes).",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path. Independent "
+              "reconstructions would shard over GPUs with no communication; one cone-beam solve "
+              "would split into z-slabs (mart_run_slabs shows that split on one GPU).",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -132,7 +132,7 @@ void uspg_free_grid(uspg_grid *g);
  * 8 bytes per entry plus 8 per ray and view, when that totals at most
  * USPG_VIEW_ROWS_MAX_BYTES, and MART then reads them as stored rows; with 1,
  * or when they do not fit, MART re-bins each view's rows from the records
- * on the fly (Alg. 1 steps 18-38).  Both give the same cells; the ray sums
+ * on the fly (the per-view part of Alg. 1).  Both give the same cells; the ray sums
  * may differ in FP32 rounding.
  * coeff_dtype: storage of the coefficients (USPG_F32 or USPG_F64).
  * colour_u, colour_v: 0 = choose the smallest valid lattice; otherwise the

@@ -105,7 +105,7 @@ class CSR:
 
 
 class Segments:
-    """Segment records of the reference view (Alg. 1 steps 1-17): per ray a
+    """Segment records of the reference view (Alg. 1, tracing of the reference view): per ray a
     run of (slice, ring, azimuth at entry, azimuth at exit)."""
 
     def __init__(self, segptr, slice_, ring, phia, phib):

@@ -13,11 +13,11 @@
  *   - the grid: ring sector counts (Sec. II.A, eq. 1) and ring heads (eq. 2);
  *   - the coefficient row of one ray by direct tracing: cylinder clip
  *     (Sec. III.A, eqs. 3-4), axial and cylindrical breakpoints sorted by
- *     distance to the source (Alg. 1, steps 3-4), per-segment slice / ring /
+ *     distance to the source (Alg. 1), per-segment slice / ring /
  *     azimuth / sector (eqs. 5-10) and the sector range of a segment inside a
  *     ring (eqs. 11-16), with lengths cut at the enumerated radial planes;
  *   - the rows of any view from the reference view by rotating the stored
- *     sector index (Sec. III.C, Alg. 1 steps 18-25);
+ *     sector index (Sec. III.C and the rotation part of Alg. 1);
  *   - a lattice colouring of the reference view's rays into cell-disjoint
  *     classes, which fixes MART's ray order;
  *   - Sp-MART (Sec. III.D, eqs. 17-19), one ray at a time;
@@ -165,7 +165,7 @@ void orc_ray(void *h, int view, int64_t ray, double *S, double *D)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Direct trace of one ray (Sec. III.A-B, Alg. 1 steps 1-17)                 */
+/* Direct trace of one ray (Sec. III.A-B, Alg. 1)                            */
 /* ------------------------------------------------------------------------ */
 
 typedef struct { double *t; int n, cap; } tvec;
@@ -279,7 +279,7 @@ static int line_breakpoints(const orc_t *o, const double *S, const double *D, do
         if (t1 <= t0) return 0;
     }
 
-    /* Alg. 1 step 3: intersections with the cylindrical planes rho = j r and
+    /* Alg. 1: intersections with the cylindrical planes rho = j r and
      * the axial planes z = z0 + k h strictly inside the chord. */
     tpush(bp, t0);
     tpush(bp, t1);
@@ -297,7 +297,7 @@ static int line_breakpoints(const orc_t *o, const double *S, const double *D, do
             if (tz > t0 && tz < t1) tpush(bp, tz);
         }
     }
-    /* Alg. 1 step 4: sort by distance to the source */
+    /* Alg. 1: sort by distance to the source */
     qsort(bp->t, bp->n, sizeof(double), cmp_double);
     return 1;
 }
@@ -453,7 +453,7 @@ int64_t orc_trace_view(void *h, int view, int64_t *rowptr, int64_t *cells, doubl
 }
 
 /* ------------------------------------------------------------------------ */
-/* Rotation of the stored reference view (Sec. III.C, Alg. 1 steps 18-25)    */
+/* Rotation of the stored reference view (Sec. III.C, Alg. 1)               */
 /* ------------------------------------------------------------------------ */
 
 /* Number q of view steps in a full turn; the rotation of view v maps sector s
@@ -703,7 +703,7 @@ int orc_mart(void *h, const int64_t *rowptr, const int64_t *cells, const double 
 /* (Sec. III.B-C, Alg. 1), binary coefficients, any number of views          */
 /* ------------------------------------------------------------------------ */
 
-/* Segment records of the line S -> D (Alg. 1 steps 3-14): every piece between
+/* Segment records of the line S -> D (Alg. 1, reference-view records): every piece between
  * consecutive cylinder / axial breakpoints longer than eps, in order along the
  * line, with the slice (eq. 6) and ring (eq. 7) of its midpoint (eq. 5) and
  * the azimuths (eq. 8) of its two end points.  No radial plane is crossed:
@@ -787,7 +787,7 @@ int64_t orc_segments_view(void *h, int64_t *segptr, int *slice, int *ring, doubl
 }
 
 /* Sectors of ring i met by a segment with reference azimuths pa, pb in view
- * `view` (Alg. 1 steps 20-35).  Both azimuths advance by the source angle
+ * `view` (per-view re-binning of Alg. 1).  Both azimuths advance by the source angle
  * theta_v = v span / p and are reduced to [0, 2 pi) (reading: eq. 10 needs
  * an angle inside the turn); eq. 10 gives the grid numbers (without the ring
  * head).  Case 1, |phi_a - phi_b| < pi (eqs. 11-13): sectors L_h = min ..
@@ -800,7 +800,7 @@ static void rebin_segment(const orc_t *o, int view, int i, double pa, double pb,
     const double theta = view * o->span / o->p;
     const int ng = o->ng[i];
     const double dphi = TWO_PI / ng;                                  /* eq. 9 */
-    double a = pa + theta, b = pb + theta;                            /* step 23 */
+    double a = pa + theta, b = pb + theta;                            /* source angle */
     if (a >= TWO_PI) a -= TWO_PI;
     if (b >= TWO_PI) b -= TWO_PI;
     int Ga = (int)floor(a / dphi), Gb = (int)floor(b / dphi);         /* eq. 10 */
@@ -926,7 +926,7 @@ int orc_rebin_conflicts(void *h, const int64_t *segptr, const int *slice, const 
 }
 
 /* MART with binary coefficients from re-binned segment records, any number
- * of views (Alg. 1 steps 19-38 with Sec. III.D): views ascending, then lattice
+ * of views (the per-view loop of Alg. 1 with Sec. III.D): views ascending, then lattice
  * classes, then the rays of a class ascending; each ray's row is rebuilt for
  * its view and updated by eq. 18 with a_j = a_max = 1.  The lattice must come
  * from orc_rebin_conflicts; the rays of a class then share no cell in any

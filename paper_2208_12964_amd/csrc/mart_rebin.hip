@@ -1,6 +1,6 @@
 // The paper's literal coefficient scheme on the device: MART over rows
 // rebuilt per view from the reference view's segment records (Sec. III.B-C,
-// Alg. 1 steps 18-38, eqs. 10-18; records and re-binning in segments.hpp).
+// the per-view part of Alg. 1, eqs. 10-18; records and re-binning in segments.hpp).
 #include <algorithm>
 
 #include "mart_row.hpp"

@@ -2,10 +2,10 @@
 // records of the reference view re-binned to the sectors of any view.
 //
 // A line is cut only at the cylindrical planes rho = j r and the axial planes
-// z = z0 + k h (Alg. 1 steps 3-4, eqs. 3-4).  Each piece longer than eps lies
+// z = z0 + k h (Alg. 1, eqs. 3-4).  Each piece longer than eps lies
 // in one ring and one slice, found from its midpoint (eqs. 5-7), and is
 // stored with the azimuths of its two ends (eq. 8).  For view v both azimuths
-// advance by the source angle theta_v = v span / p (Alg. 1 step 23); eq. 10
+// advance by the source angle theta_v = v span / p (Alg. 1); eq. 10
 // turns them into sector numbers and the sectors between them (eqs. 11-16,
 // two cases) are the cells the piece meets, each with coefficient 1 (binary
 // weights, Sec. III.B).  Nothing requires the view step to be a whole number
@@ -150,12 +150,12 @@ USPG_HD int segments_of_ray(const walk::TraceGeo &G, int64_t r, Sink &sink)
 }
 
 // Sectors met in view `view` by a segment of a ring of ng sectors with
-// reference azimuths pa, pb (Alg. 1 steps 20-35): first sector and count,
+// reference azimuths pa, pb (per-view re-binning of Alg. 1): first sector and count,
 // the sectors being first, first + 1, ... modulo ng.
 USPG_HD inline void rebin_range(int ng, double pa, double pb, double theta, int &first, int &count)
 {
     const double dphi = kTwoPiS / ng;                 // eq. 9
-    double a = pa + theta, b = pb + theta;            // step 23
+    double a = pa + theta, b = pb + theta;            // source angle
     if (a >= kTwoPiS) a -= kTwoPiS;
     if (b >= kTwoPiS) b -= kTwoPiS;
     int Ga = (int)floor(a / dphi), Gb = (int)floor(b / dphi);   // eq. 10

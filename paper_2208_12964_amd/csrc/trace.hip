@@ -1,4 +1,4 @@
-// Reference-view tracing on the device (Sec. III.A-B, Alg. 1 steps 1-17).
+// Reference-view tracing on the device (Sec. III.A-B, Alg. 1).
 // One thread walks one view-0 ray in FP64 (trace_walk.hpp).  Two passes with
 // identical arithmetic: the first counts entries per ray, the second writes
 // them at the scanned offsets.
