@@ -209,7 +209,12 @@ void uspg_free_coeffs(uspg_coeffs *c);
  *        (eq. 19) and synchronises the stream once per sweep.
  * sweeps_done: host, nullable; receives the number of sweeps run (written
  *        before return, so only meaningful after the stream is synchronised
- *        when tol == 0 -- it is then simply n_sweeps). */
+ *        when tol == 0 -- it is then simply n_sweeps).
+ * Graph capture: with tol == 0 the call enqueues kernels and device-to-device
+ * copies only (no allocation, memset or host wait), so it may be recorded
+ * into a HIP graph by capturing `stream`; each replay reads proj and image
+ * as they are when it runs.  tol > 0 on a capturing stream returns
+ * USPG_E_ARG before anything is enqueued. */
 size_t uspg_mart_workspace_bytes(const uspg_coeffs *c, int32_t dtype, double tol);
 
 int mart_run(const uspg_coeffs *c, int32_t dtype, const void *proj, void *image, void *work,
@@ -220,7 +225,8 @@ int mart_run(const uspg_coeffs *c, int32_t dtype, const void *proj, void *image,
  * accumulators and turns timing on: every later mart_run records one HIP
  * event pair on its stream around its sequence of (view, class) batch
  * kernels (nothing between them), synchronises the stream at its end and
- * adds the elapsed time and the number of batch launches.  enable = 0 turns
+ * adds the elapsed time and the number of batch launches (calls on a stream
+ * under graph capture are not timed).  enable = 0 turns
  * timing off.  batch_ms and batch_launches (host, nullable) receive the
  * totals so far.  Process-wide; not meant for concurrent mart_run calls. */
 int uspg_mart_timing(int32_t enable, double *batch_ms, int64_t *batch_launches);

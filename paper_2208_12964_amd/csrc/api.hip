@@ -374,6 +374,8 @@ int mart_run(const uspg_coeffs *c, int32_t dtype, const void *proj, void *image,
     if (work_bytes < uspg_mart_workspace_bytes(c, dtype, tol)) return fail(USPG_E_NOMEM, "work space too small");
     int rc = check_device(c->device);
     if (rc != USPG_OK) return rc;
+    if (tol > 0 && stream_capturing((hipStream_t)stream))
+        return fail(USPG_E_ARG, "tol > 0 synchronises the stream once per sweep and cannot be graph-captured");
     return mart_launch(c, dtype, proj, image, work, n_sweeps, beta, tol, sweeps_done, (hipStream_t)stream);
 }
 

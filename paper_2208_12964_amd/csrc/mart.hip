@@ -171,7 +171,7 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
     const int nch = pick_nch(c->max_row);
     const int K = c->Ku * c->Kv;
     int done = 0;
-    const bool timing = g_timing.load() != 0 && tol == 0;
+    const bool timing = mart_timing_on(s) && tol == 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int64_t launches = 0;
     if (timing) {
@@ -254,7 +254,15 @@ int layout_permute(const uspg_coeffs *c, int dtype, const void *src, void *dst, 
     return USPG_OK;
 }
 
-bool mart_timing_on() { return g_timing.load() != 0; }
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+// Timing records and waits on events, which a stream under graph capture
+// cannot do: captured calls are not timed.
+bool mart_timing_on(hipStream_t s) { return g_timing.load() != 0 && !stream_capturing(s); }
 
 void mart_timing_add(int64_t ns, int64_t launches)
 {

@@ -229,7 +229,7 @@ int run_segments(const uspg_coeffs *c, const T *proj, T *image, void *work, int 
                                                                           : 64;
     const int rays_per_block = G == kBlock ? 1 : kWaves * (64 / G);
     int done = 0;
-    const bool timing = mart_timing_on() && tol == 0;
+    const bool timing = mart_timing_on(s) && tol == 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int64_t launches = 0;
     if (timing) {

@@ -144,7 +144,8 @@ int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, 
                 int n_sweeps, double beta, double tol, int32_t *sweeps_done, hipStream_t s);
 int mart_timing(int enable, double *batch_ms, int64_t *batch_launches);
 // Whether batch timing is on, and adding a timed run of launches to it.
-bool mart_timing_on();
+bool stream_capturing(hipStream_t s);
+bool mart_timing_on(hipStream_t s);
 void mart_timing_add(int64_t ns, int64_t launches);
 // One (view, class) batch of the single-problem kernel over explicit rows
 // of (id, coefficient) pairs of float coefficients (shift added mod wtot);
