@@ -55,7 +55,7 @@ def counter_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cone-256r-32v-hc")
     ap.add_argument("--mode", default="single", choices=["single", "batch2d", "serve", "paper", "slabs"],
@@ -513,7 +513,8 @@ def main():
     nnz, lattice = rec[0][1], rec[0][2]
     updates = w.n_views * nnz * w.sweeps
     build_ms = np.mean([r[0][0].elapsed_time(r[0][1]) for r in rec])
-    mart_ms = np.mean([r[0][1].elapsed_time(r[0][2]) for r in rec])
+    mart_each = [r[0][1].elapsed_time(r[0][2]) for r in rec]
+    mart_ms = np.mean(mart_each)
     remap_ms = np.mean([r[0][2].elapsed_time(r[0][3]) for r in rec])
     n_launch = w.sweeps * w.n_views * lattice[0] * lattice[1]
     assert batch_launches == n_launch * args.steps
@@ -533,6 +534,8 @@ def main():
                    "nnz_ref": nnz, "lattice": list(lattice), "remap": f"{nc}x{nc}x{w.n_slices}"},
         "sweeps_per_s": w.sweeps / (mart_ms * 1e-3),
         "phases_ms": {"build": build_ms, "mart": mart_ms, "remap": remap_ms},
+        "mart_ms_over_steps": {"median": float(np.median(mart_each)), "min": float(np.min(mart_each)),
+                               "max": float(np.max(mart_each))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
