@@ -21,7 +21,10 @@
  *   - a lattice colouring of the reference view's rays into cell-disjoint
  *     classes, which fixes MART's ray order;
  *   - Sp-MART (Sec. III.D, eqs. 17-19), one ray at a time;
- *   - the USPG -> Cartesian remap (Sec. II.B).
+ *   - the USPG -> Cartesian remap (Sec. II.B).  Parity unpinned: where the
+ *     bijection mode's numbering of a square ring starts and which way it
+ *     runs (a reading of a figure the text does not describe); its pixel
+ *     counts and the one-to-one property are pinned.
  *
  * Readings where the paper is silent or garbled are listed with the functions
  * that take them.  Status codes: 0 ok, -1 bad argument, -2 the grid is not
@@ -982,7 +985,8 @@ int orc_mart_rebin(void *h, const int64_t *segptr, const int *slice, const int *
  * mode 1 (bijection, Sec. II.B, Fig. 2): for the paper's grid (n_g = 4(2n-1))
  *   with nc = 2 Nr, square ring n (pixels with max(|X|,|Y|) = 2n - 1) has as
  *   many pixels as circular ring n; both are numbered anticlockwise from the
- *   +x axis (reading of Fig. 3) and matched one to one.
+ *   +x axis (reading of Fig. 3; parity unpinned for that start and
+ *   direction) and matched one to one.
  * cart is [Nz][nc][nc], row index iy (ascending y), column ix. */
 int orc_remap(void *h, const double *f, double *cart, int nc, int mode)
 {
