@@ -239,7 +239,8 @@ int uspg_mart_timing(int32_t enable, double *batch_ms, int64_t *batch_launches);
  * BIJECTION: paper grid only (sector rule PAPER) with nc = 2 n_rings: square
  *   ring n (pixels with max(|2ix+1-nc|, |2iy+1-nc|) = 2n - 1) and circular
  *   ring n hold the same number of cells and are matched one to one, both
- *   numbered anticlockwise from the +x axis. */
+ *   numbered anticlockwise from the +x axis.
+ * One kernel on `stream`: the call may be captured into a HIP graph. */
 int uspg_to_cartesian(const uspg_grid *g, int32_t dtype, const void *image, void *cart,
                       int32_t nc, int32_t mode, void *stream);
 

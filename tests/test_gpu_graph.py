@@ -1,8 +1,9 @@
-"""mart_run recorded into a HIP graph by stream capture (tol = 0): every replay,
-with eager work and synchronisations between replays, equals the eager call
-bit for bit, for stored reference rows, kept literal-scheme view rows and
-rows re-binned on the fly.  tol > 0 on a capturing stream is refused before
-anything is enqueued, and captured calls are not timed."""
+"""mart_run (tol = 0) and the Cartesian remap recorded into a HIP graph by
+stream capture: every replay, with eager work and synchronisations between
+replays, equals the eager calls bit for bit, for stored reference rows, kept
+literal-scheme view rows and rows re-binned on the fly.  tol > 0 on a
+capturing stream is refused before anything is enqueued, and captured calls
+are not timed."""
 import pytest
 import torch
 
@@ -37,21 +38,27 @@ def test_captured_mart_run_replays_equal_eager(U, kind, dtype):
     proj = torch.as_tensor(synth.make_projections(w), dtype=dtype, device=dev).contiguous()
     eager = torch.ones(grid.n_cells, dtype=dtype, device=dev)
     U.mart(co, proj, eager, w.sweeps, w.beta)
+    nc = 2 * w.n_rings
+    cart_eager = U.to_cartesian(grid, eager, nc)
     torch.cuda.synchronize()
 
     img = torch.ones(grid.n_cells, dtype=dtype, device=dev)
     work = torch.empty(co.workspace_bytes(dtype), dtype=torch.uint8, device=dev)
     U.mart_timing(True)
     g = torch.cuda.CUDAGraph()
+    cart = torch.empty_like(cart_eager)
     with torch.cuda.graph(g):
         U.mart(co, proj, img, w.sweeps, w.beta, work=work)
+        U.to_cartesian(grid, img, nc, out=cart)
     torch.cuda.synchronize()
     for rep in range(4):
         img.fill_(1.0)                                   # a fill kernel, not a memset node
+        cart.fill_(-1.0)
         g.replay()
         junk = torch.randn(1 << 18, device=dev).sum()    # eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(img, eager), (kind, rep)
+        assert torch.equal(cart, cart_eager), (kind, rep)
         assert torch.isfinite(junk)
     _, launches = U.mart_timing(False)
     assert launches == 0                                 # the captured call was not timed
