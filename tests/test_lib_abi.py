@@ -40,3 +40,13 @@ def test_error_path_without_device_work():
     h = C.c_void_p()
     assert L.uspg_build_grid(None, C.byref(h)) == -1
     assert b"null" in L.uspg_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the one-GPU refusal happens before torch or the library is touched
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout
