@@ -112,6 +112,24 @@ def test_row_sums_equal_chords_cone():
             assert math.isclose(lens.sum(), ch, rel_tol=1e-12, abs_tol=1e-13)
 
 
+def test_row_sums_equal_chords_fan():
+    # fan beam (Table 1 scans) with intersection lengths: each row sums to the
+    # ray's chord through the disk, in the reference view and a rotated one
+    w = synth.small_cone(n_rings=20, n_views=6, det=30, m=6).with_(
+        geometry="fan2d", n_slices=1, height=0.0, det_v=1)
+    o = Oracle(w)
+    hit = 0
+    for v in (0, 2):
+        csr = o.trace_view(v)
+        for r in range(o.n_rays):
+            S, D = o.ray(v, r)
+            _, lens = csr.row(r)
+            ch = chord_length(S, D, w.radius)
+            assert math.isclose(lens.sum(), ch, rel_tol=1e-12, abs_tol=1e-14)
+            hit += ch > 0
+    assert hit > o.n_rays   # most rays of both views cross the disk
+
+
 def test_tangent_and_missing_rays_are_empty():
     w = synth.get("par2d-32r-8v")
     o = Oracle(w)
