@@ -78,9 +78,23 @@ def test_paper_grid_with_whole_sector_shift_uses_lengths(U):
     """On the paper's grid the view step is a whole number of sectors in
     every ring only for q | 4 (n_g = 4 (2n - 1)): four views over a turn run
     through the stored-length path; 50 views need the literal scheme."""
-    w = synth.paper_fan(64, 4).with_(rebin=False, binary=False, quarter=False)
+    w = synth.paper_fan(64, 4).with_(rebin=False, binary=False, quarter=False, sweeps=5)
     g = U.Grid.from_workload(w)
     U.Coeffs.from_workload(g, w)
     with pytest.raises(U.USPGError) as e:
         U.Coeffs.from_workload(g, w.with_(n_views=50))
     assert e.value.code == -2
+    # the stored-length solve on the paper's grid, and its bijection remap,
+    # equal the oracle's
+    dev = torch.device("cuda:0")
+    P = synth.make_projections(w)
+    o = Oracle(w, nthreads=NTHREADS)
+    f_ref, _, lat = o.reconstruct(P)
+    for dtype, tol in ((torch.float64, 1e-10), (torch.float32, 1e-4)):
+        img, _, g2, co = U.reconstruct(w, torch.as_tensor(P, device=dev), dtype=dtype, remap_nc=0)
+        assert co.lattice == lat
+        f = img.cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(f - f_ref)) / np.max(np.abs(f_ref)) <= tol
+        cart = U.to_cartesian(g2, img, 2 * w.n_rings, mode="bijection").cpu().numpy().astype(np.float64)
+        cref = o.remap(f_ref, 2 * w.n_rings, mode="bijection")
+        assert np.max(np.abs(cart - cref)) <= tol * np.max(np.abs(cref))
