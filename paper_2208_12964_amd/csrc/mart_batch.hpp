@@ -26,8 +26,10 @@ struct BatchArgs {
 
 // The launcher caps the grid (16 workgroups per CU) and each wavefront
 // strides through the class by the grid's wavefront count; the rays of a
-// class share no cell, so the assignment changes no result.
-template <class T, class TC, int MAXC>
+// class share no cell, so the assignment changes no result.  NT: load the
+// coefficients with the non-temporal hint (the launcher's choice by the
+// size of the coefficient set; the same bits either way).
+template <class T, class TC, int MAXC, bool NT = true>
 __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
 {
     const int lane = threadIdx.x & 63;
@@ -39,7 +41,7 @@ __global__ __launch_bounds__(kBlock) void mart_batch(BatchArgs<T, TC> A)
         const int64_t beg = A.rowptr[r];
         const int n = (int)(A.rowptr[r + 1] - beg);
         if (n == 0) continue;
-        row::mart_row<T, TC, MAXC>(A.f, A.shift, A.wtot, A.beta, A.co + beg, n, A.P[r], lane);
+        row::mart_row<T, TC, MAXC, NT>(A.f, A.shift, A.wtot, A.beta, A.co + beg, n, A.P[r], lane);
     }
 }
 

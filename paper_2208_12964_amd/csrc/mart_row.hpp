@@ -52,19 +52,30 @@ __device__ __forceinline__ T fmadd(T a, T b, T c) { return __builtin_fma(a, b, c
 template <>
 __device__ __forceinline__ float fmadd<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-// Non-temporal load of one (id, coefficient) pair: one vector load.
+// Load of one (id, coefficient) pair: one vector load.  NT: with the
+// non-temporal hint, for coefficient sets that stream through caches too
+// small to hold them; without it, a set that fits the last-level cache
+// together with the image stays there from one view to the next.
+template <bool NT = true>
 __device__ __forceinline__ void load_coef(const Coef<float> *p, uint32_t &id, float &a)
 {
     typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-    const u2 e = __builtin_nontemporal_load(reinterpret_cast<const u2 *>(p));
+    const u2 *q = reinterpret_cast<const u2 *>(p);
+    u2 e;
+    if constexpr (NT) e = __builtin_nontemporal_load(q);
+    else e = *q;
     id = e.x;
     a = __uint_as_float(e.y);
 }
 
+template <bool NT = true>
 __device__ __forceinline__ void load_coef(const Coef<double> *p, uint32_t &id, double &a)
 {
     typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-    const u4 e = __builtin_nontemporal_load(reinterpret_cast<const u4 *>(p));
+    const u4 *q = reinterpret_cast<const u4 *>(p);
+    u4 e;
+    if constexpr (NT) e = __builtin_nontemporal_load(q);
+    else e = *q;
     id = e.x;
     const unsigned long long bits = ((unsigned long long)e.w << 32) | e.z;
     __builtin_memcpy(&a, &bits, sizeof(a));
@@ -74,7 +85,7 @@ __device__ __forceinline__ void load_coef(const Coef<double> *p, uint32_t &id, d
 // clamped and coefficients masked instead of branching, so every load of a
 // phase is issued before the first wait: the ids and coefficients, then all
 // gathers, then the reductions, then the predicated scatter.
-template <class T, class TC, int C, class Img>
+template <class T, class TC, int C, bool NT = true, class Img>
 __device__ __forceinline__ void row_in_registers(Img img, uint32_t shift, uint32_t wtot, T beta,
                                                  const Coef<TC> *co, int n, T P, int lane)
 {
@@ -86,11 +97,11 @@ __device__ __forceinline__ void row_in_registers(Img img, uint32_t shift, uint32
     for (int k = 0; k < C; ++k) {
         const int j = lane + 64 * k;
         const int jj = j < n ? j : last;
-        // the coefficient stream is read once per view: non-temporal loads
-        // keep it from evicting the image from the caches
+        // the coefficient stream is read once per view: for large sets
+        // non-temporal loads keep it from evicting the image from the caches
         uint32_t cid;
         TC ca;
-        load_coef(co + jj, cid, ca);
+        load_coef<NT>(co + jj, cid, ca);
         const uint32_t t = cid + shift;
         id[k] = t >= wtot ? t - wtot : t;
         av[k] = (T)ca * (j < n ? T(1) : T(0));   // masked, not branched
@@ -140,7 +151,7 @@ __device__ void row_streamed(Img img, uint32_t shift, uint32_t wtot, T beta, con
 
 // One ray: dispatch on its wave-uniform chunk count to a compile-time
 // unrolled register body (rows longer than 64 * MAXC are streamed).
-template <class T, class TC, int MAXC, class Img>
+template <class T, class TC, int MAXC, bool NT = true, class Img>
 __device__ __forceinline__ void mart_row(Img img, uint32_t shift, uint32_t wtot, T beta, const Coef<TC> *co, int n,
                                          T P, int lane)
 {
@@ -149,7 +160,7 @@ __device__ __forceinline__ void mart_row(Img img, uint32_t shift, uint32_t wtot,
         // 17 .. MAXC chunks: one register body of MAXC chunks, the entries
         // past the row masked (same sums as the streamed loop)
         if (chunks > 16 && chunks <= MAXC) {
-            row_in_registers<T, TC, MAXC>(img, shift, wtot, beta, co, n, P, lane);
+            row_in_registers<T, TC, MAXC, NT>(img, shift, wtot, beta, co, n, P, lane);
             return;
         }
     }
@@ -161,7 +172,7 @@ __device__ __forceinline__ void mart_row(Img img, uint32_t shift, uint32_t wtot,
 #define USPG_ROW_CASE(C)                                                                          \
     case C:                                                                                       \
         if (C <= MAXC)                                                                            \
-            row_in_registers<T, TC, (C <= MAXC ? C : 1)>(img, shift, wtot, beta, co, n, P, lane); \
+            row_in_registers<T, TC, (C <= MAXC ? C : 1), NT>(img, shift, wtot, beta, co, n, P, lane); \
         break;
         USPG_ROW_CASE(1) USPG_ROW_CASE(2) USPG_ROW_CASE(3) USPG_ROW_CASE(4)
         USPG_ROW_CASE(5) USPG_ROW_CASE(6) USPG_ROW_CASE(7) USPG_ROW_CASE(8)
