@@ -37,6 +37,7 @@ struct uspg_batch {
     size_t lds_bytes = 0;         // dynamic LDS of the launch
     int maxc = 16;
     bool any_kept = false;        // some problem runs kept per-view rows
+    bool nt = true;               // lockstep coefficient loads with the non-temporal hint
     std::vector<int> lds_mode;    // per problem
     // lockstep
     uspg::DevBuf d_dyn, d_wgbeg;  // per-problem run arguments, workgroup prefix
@@ -46,7 +47,7 @@ struct uspg_batch {
     // the lockstep launch sequence captured as one graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    int g_steps = -1, g_block = -1, g_grid = -1;
+    int g_steps = -1, g_block = -1, g_grid = -1, g_nt = -1;
 };
 
 namespace uspg {
@@ -152,7 +153,7 @@ __global__ void mart_multi(MultiArgs<T> A)
 // prefix range holds it; its wavefronts take that problem's rays of the
 // current (view, class) in order.  (Capping this grid and striding, as the
 // single-problem batch kernel does, made it 6-42 % slower.)
-template <class T, class TC, int MAXC, bool KEPT>
+template <class T, class TC, int MAXC, bool KEPT, bool NT>
 __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, const ProblemDyn<T> *dyn,
                                                      const int *wgbeg, int n, int step)
 {
@@ -184,18 +185,18 @@ __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, co
     if (len == 0) return;
     uint32_t shift;
     const Coef<TC> *co = view_coef<TC, KEPT>(S, v, shift);
-    mart_row<T, TC, MAXC>(D.f, shift, S.Wtot, D.beta, co + beg, len, D.P[(int64_t)v * S.nrays + r],
-                          threadIdx.x & 63);
+    mart_row<T, TC, MAXC, NT>(D.f, shift, S.Wtot, D.beta, co + beg, len, D.P[(int64_t)v * S.nrays + r],
+                              threadIdx.x & 63);
 }
 
 // The step sequence is captured once into a graph (per step count and launch
 // shape) and replayed with one graph launch; the run arguments it reads live
 // in d_dyn, refreshed before every replay.
-template <class T, class TC, int MAXC, bool KEPT>
+template <class T, class TC, int MAXC, bool KEPT, bool NT>
 int lockstep_typed(uspg_batch *b, int steps, hipStream_t s)
 {
     const int grid = b->wgbeg[b->n];
-    if (!b->gexec || b->g_steps != steps || b->g_block != b->block || b->g_grid != grid) {
+    if (!b->gexec || b->g_steps != steps || b->g_block != b->block || b->g_grid != grid || b->g_nt != (int)NT) {
         if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
         if (b->graph) (void)hipGraphDestroy(b->graph);
         b->gexec = nullptr;
@@ -207,7 +208,7 @@ int lockstep_typed(uspg_batch *b, int steps, hipStream_t s)
             rc = fail(USPG_E_HIP, "hipStreamBeginCapture failed");
         } else {
             for (int t = 0; t < steps; ++t)
-                hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC, KEPT>), dim3(grid), dim3(b->block), 0, cs,
+                hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC, KEPT, NT>), dim3(grid), dim3(b->block), 0, cs,
                                    b->d_static.as<ProblemStatic>(), b->d_dyn.as<ProblemDyn<T>>(),
                                    b->d_wgbeg.as<int>(), b->n, t);
             if (hipStreamEndCapture(cs, &b->graph) != hipSuccess ||
@@ -219,24 +220,27 @@ int lockstep_typed(uspg_batch *b, int steps, hipStream_t s)
         b->g_steps = steps;
         b->g_block = b->block;
         b->g_grid = grid;
+        b->g_nt = (int)NT;
     }
     USPG_HIP(hipGraphLaunch(b->gexec, s));
     return USPG_OK;
 }
 
+template <class T, class TC, bool KEPT, bool NT>
+int lockstep_chunks(uspg_batch *b, int steps, hipStream_t s)
+{
+    if (b->maxc <= 2) return lockstep_typed<T, TC, 2, KEPT, NT>(b, steps, s);
+    if (b->maxc <= 4) return lockstep_typed<T, TC, 4, KEPT, NT>(b, steps, s);
+    if (b->maxc <= 8) return lockstep_typed<T, TC, 8, KEPT, NT>(b, steps, s);
+    return lockstep_typed<T, TC, 16, KEPT, NT>(b, steps, s);
+}
+
 template <class T, class TC>
 int lockstep_maxc(uspg_batch *b, int steps, hipStream_t s)
 {
-    if (b->any_kept) {
-        if (b->maxc <= 2) return lockstep_typed<T, TC, 2, true>(b, steps, s);
-        if (b->maxc <= 4) return lockstep_typed<T, TC, 4, true>(b, steps, s);
-        if (b->maxc <= 8) return lockstep_typed<T, TC, 8, true>(b, steps, s);
-        return lockstep_typed<T, TC, 16, true>(b, steps, s);
-    }
-    if (b->maxc <= 2) return lockstep_typed<T, TC, 2, false>(b, steps, s);
-    if (b->maxc <= 4) return lockstep_typed<T, TC, 4, false>(b, steps, s);
-    if (b->maxc <= 8) return lockstep_typed<T, TC, 8, false>(b, steps, s);
-    return lockstep_typed<T, TC, 16, false>(b, steps, s);
+    if (b->any_kept)
+        return b->nt ? lockstep_chunks<T, TC, true, true>(b, steps, s) : lockstep_chunks<T, TC, true, false>(b, steps, s);
+    return b->nt ? lockstep_chunks<T, TC, false, true>(b, steps, s) : lockstep_chunks<T, TC, false, false>(b, steps, s);
 }
 
 template <class T, class TC, int MAXC, bool KEPT>
@@ -370,6 +374,21 @@ int upload_static(uspg_batch *b)
         b->any_kept = b->any_kept || kept_rows(c);
     }
     b->maxc = (maxrow + 63) / 64;
+    // lockstep coefficient loads: non-temporal unless every coefficient set
+    // (each counted once) and image of the batch fit the last-level cache
+    {
+        std::vector<const uspg_coeffs *> sets;
+        size_t coef_bytes = 0, image_bytes = 0;
+        for (int i = 0; i < b->n; ++i) {
+            const uspg_coeffs *c = b->co[i];
+            if (std::find(sets.begin(), sets.end(), c) == sets.end()) {
+                sets.push_back(c);
+                coef_bytes += coef_set_bytes(c);
+            }
+            image_bytes += (size_t)solve_cells(c) * tsz;
+        }
+        b->nt = stream_coefs(coef_bytes, image_bytes);
+    }
     // lockstep: enough workgroups for each problem's largest class
     const int waves = b->block / 64;
     b->wgbeg.assign(b->n + 1, 0);
@@ -474,12 +493,12 @@ int engine_upload(uspg_engine *e, hipStream_t s)
 // in order: the lockstep steps go first, then the steps of each wide
 // problem in one run, which keeps that problem's image in the caches
 // (two 256-ring problems alternating step by step took 10 % longer).
-template <class T, class TC, int MAXC, bool KEPT>
+template <class T, class TC, int MAXC, bool KEPT, bool NT>
 int engine_launch(uspg_engine *e, int steps, hipStream_t s)
 {
     if (!e->table.empty())
         for (int t = 0; t < steps; ++t)
-            hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC, KEPT>), dim3(e->grid), dim3(64 * kEngineWaves), 0, s,
+            hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC, KEPT, NT>), dim3(e->grid), dim3(64 * kEngineWaves), 0, s,
                                e->d_static.as<ProblemStatic>(), e->d_dyn.as<ProblemDyn<T>>(),
                                e->d_wgbeg.as<int>(), (int)e->table.size(), t);
     for (int id : e->wide) {
@@ -498,26 +517,42 @@ int engine_launch(uspg_engine *e, int steps, hipStream_t s)
     return USPG_OK;
 }
 
+template <class T, class TC, bool KEPT, bool NT>
+int engine_chunks(uspg_engine *e, int64_t chunks, int steps, hipStream_t s)
+{
+    if (chunks <= 2) return engine_launch<T, TC, 2, KEPT, NT>(e, steps, s);
+    if (chunks <= 4) return engine_launch<T, TC, 4, KEPT, NT>(e, steps, s);
+    if (chunks <= 8) return engine_launch<T, TC, 8, KEPT, NT>(e, steps, s);
+    return engine_launch<T, TC, 16, KEPT, NT>(e, steps, s);
+}
+
 template <class T, class TC>
 int engine_maxc(uspg_engine *e, int steps, hipStream_t s)
 {
     int64_t longest = 0;
     bool kept = false;
+    // the lockstep launch reads every table problem's rows and image: the
+    // coefficient loads keep the non-temporal hint unless they all fit the
+    // last-level cache (each coefficient set counted once)
+    std::vector<const uspg_coeffs *> sets;
+    size_t coef_bytes = 0, image_bytes = 0;
     for (int id : e->table) {
-        longest = std::max<int64_t>(longest, stored_max_row(e->slots[id].c));
-        kept = kept || kept_rows(e->slots[id].c);
+        const uspg_coeffs *c = e->slots[id].c;
+        longest = std::max<int64_t>(longest, stored_max_row(c));
+        kept = kept || kept_rows(c);
+        if (std::find(sets.begin(), sets.end(), c) == sets.end()) {
+            sets.push_back(c);
+            coef_bytes += coef_set_bytes(c);
+        }
+        image_bytes += (size_t)solve_cells(c) * sizeof(T);
     }
+    const bool nt = stream_coefs(coef_bytes, image_bytes);
     const int64_t chunks = (longest + 63) / 64;
-    if (kept) {
-        if (chunks <= 2) return engine_launch<T, TC, 2, true>(e, steps, s);
-        if (chunks <= 4) return engine_launch<T, TC, 4, true>(e, steps, s);
-        if (chunks <= 8) return engine_launch<T, TC, 8, true>(e, steps, s);
-        return engine_launch<T, TC, 16, true>(e, steps, s);
-    }
-    if (chunks <= 2) return engine_launch<T, TC, 2, false>(e, steps, s);
-    if (chunks <= 4) return engine_launch<T, TC, 4, false>(e, steps, s);
-    if (chunks <= 8) return engine_launch<T, TC, 8, false>(e, steps, s);
-    return engine_launch<T, TC, 16, false>(e, steps, s);
+    if (kept)
+        return nt ? engine_chunks<T, TC, true, true>(e, chunks, steps, s)
+                  : engine_chunks<T, TC, true, false>(e, chunks, steps, s);
+    return nt ? engine_chunks<T, TC, false, true>(e, chunks, steps, s)
+              : engine_chunks<T, TC, false, false>(e, chunks, steps, s);
 }
 
 }  // namespace

@@ -131,8 +131,6 @@ int pick_nch(int max_row) { return (max_row + 63) / 64; }
 // bound between them is a choice, not a measured crossover.
 constexpr size_t kCacheResidentBytes = size_t(192) << 20;
 
-bool stream_coefs(size_t coef_bytes, size_t image_bytes) { return coef_bytes + image_bytes > kCacheResidentBytes; }
-
 // Arguments of batch (view v, class cl) of problem c on the wedge-major
 // image f: the class's rays, the view's projections and shift, and the
 // capped grid.
@@ -272,6 +270,8 @@ int layout_permute(const uspg_coeffs *c, int dtype, const void *src, void *dst, 
     USPG_HIP(hipGetLastError());
     return USPG_OK;
 }
+
+bool stream_coefs(size_t coef_bytes, size_t image_bytes) { return coef_bytes + image_bytes > kCacheResidentBytes; }
 
 bool stream_capturing(hipStream_t s)
 {

@@ -145,6 +145,12 @@ int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, 
 int mart_timing(int enable, double *batch_ms, int64_t *batch_launches);
 // Whether batch timing is on, and adding a timed run of launches to it.
 bool stream_capturing(hipStream_t s);
+// Whether coefficient loads take the non-temporal hint: true unless the
+// coefficient sets and images a launch reads fit the last-level cache.
+bool stream_coefs(size_t coef_bytes, size_t image_bytes);
+// Device bytes of the coefficient rows a solve reads (kept view rows or the
+// stored reference rows).
+inline size_t coef_set_bytes(const uspg_coeffs *c) { return c->view_coef.p ? c->view_coef.bytes : c->coef.bytes; }
 bool mart_timing_on(hipStream_t s);
 void mart_timing_add(int64_t ns, int64_t launches);
 // One (view, class) batch of the single-problem kernel over explicit rows
