@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--slots", default="256:2,128:8,64:32",
                     help="serve: slots per lane as lane:count pairs (lane = ring count with --lanes rings)")
     ap.add_argument("--fifo", action="store_true", help="serve: also run the one-at-a-time baseline")
+    ap.add_argument("--streams", default="lane", choices=["lane", "shared"],
+                    help="serve: one stream per lane (calls of different lanes overlap) or one shared stream")
     return ap.parse_args()
 
 
@@ -264,7 +266,7 @@ def bench_serve(args):
     budget = int(args.budget_gib * 2**30)
     slots = {int(a): int(b) for a, b in (x.split(":") for x in args.slots.split(",") if x)}
     srv = Server(geo.get, budget=budget, lane_of=lane_of, max_slots=slots, steps_per_call=args.steps_per_call,
-                 keep_results=False)
+                 keep_results=False, shared_stream=args.streams == "shared")
     reqs = make(items)
     report = lambda st: say("serve: t=%.0f s completed %d queued %d active %d" % (   # noqa: E731
         st["wall_s"], st["completed"], st.get("queued", 0), st.get("active", 0)))
@@ -277,7 +279,7 @@ def bench_serve(args):
            "ms_per_step": st["wall_s"] * 1e3 / max(1, st["completed"]), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "serve-poisson", "rate_per_s": args.rate, "duration_s": args.duration,
-                      "requests": len(items), "budget_gib": args.budget_gib, "lanes": args.lanes,
+                      "requests": len(items), "budget_gib": args.budget_gib, "lanes": args.lanes, "streams": args.streams,
                       "slots": args.slots,
                       "steps_per_call": args.steps_per_call},
            "latency": {k: v for k, v in st.items() if k.endswith("_s") or k.endswith("_by_key_s")},

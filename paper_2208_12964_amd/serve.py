@@ -130,9 +130,9 @@ def percentile(xs, q: float) -> float:
 
 
 class _Lane:
-    def __init__(self, max_slots, dtype, device):
+    def __init__(self, max_slots, dtype, device, stream=None):
         self.engine = Engine(max_slots, dtype)
-        self.stream = torch.cuda.Stream(device=device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         self.max_slots = max_slots
         self.slots = {}        # slot -> Request
         self.gstep = 0
@@ -148,11 +148,14 @@ class Server:
     `lane_of(key) -> int`; `budget` bytes for admitted requests; at most
     `max_slots` requests per lane (an int, or a dict lane -> count with 64
     for lanes it does not name); each step call advances a lane by at most
-    `steps_per_call` steps; at most `depth` calls per lane are in flight."""
+    `steps_per_call` steps; at most `depth` calls per lane are in flight.
+    `shared_stream`: every lane issues its step calls on one stream (calls of
+    different lanes then run one after another instead of side by side)."""
 
     def __init__(self, geometry, budget: int, lane_of=lambda key: key[0], max_slots=64,
                  steps_per_call: int = 64, depth: int = 2, dtype=torch.float32, device="cuda:0",
-                 skip_ahead: bool = True, max_wait: float = 1.0, keep_results: bool = True):
+                 skip_ahead: bool = True, max_wait: float = 1.0, keep_results: bool = True,
+                 shared_stream: bool = False):
         self.cache = GeometryCache(geometry)
         self.lane_of = lane_of
         self.admission = Admission(budget, skip_ahead, max_wait)
@@ -162,6 +165,7 @@ class Server:
         self.dtype = dtype
         self.device = torch.device(device)
         self.keep_results = keep_results
+        self.shared = torch.cuda.Stream(device=self.device) if shared_stream else None
         self.lanes = {}
         self.queue = deque()
         self.rejected = []
@@ -170,7 +174,7 @@ class Server:
     def _lane(self, lid):
         if lid not in self.lanes:
             ms = self.max_slots.get(lid, 64) if isinstance(self.max_slots, dict) else self.max_slots
-            self.lanes[lid] = _Lane(ms, self.dtype, self.device)
+            self.lanes[lid] = _Lane(ms, self.dtype, self.device, self.shared)
         return self.lanes[lid]
 
     def prepare(self, r: Request):
