@@ -61,8 +61,7 @@ def _load():
     lib.orc_conflict_offsets.argtypes = [P, P, P, P]
     lib.orc_colour.argtypes = [P, P, P, P]
     lib.orc_mart_ray.argtypes = [P, P, I64, D, P, D]
-    lib.orc_mart.argtypes = [P, P, P, P, I, I, I, I, P, P, I, D, D, P, I]
-    lib.orc_tiles_ok.argtypes = [P, P, I, I]
+    lib.orc_mart.argtypes = [P, P, P, P, I, I, P, P, I, D, D, P, I]
     lib.orc_remap.argtypes = [P, P, P, I, I]
     lib.orc_segments_line.argtypes = [P, P, P, P, P, P, P, I, P]
     lib.orc_segments_view.restype = I64
@@ -210,20 +209,15 @@ class Oracle:
         return ku.value, kv.value
 
     # -- MART -----------------------------------------------------------------
-    def tiles_ok(self, csr0: CSR, tiles) -> bool:
-        mark = np.ascontiguousarray(self.conflict_offsets(csr0).ravel())
-        return self.lib.orc_tiles_ok(self._h, _ptr(mark), int(tiles[0]), int(tiles[1])) == 0
-
-    def mart(self, csr0: CSR, lattice, P, f0, sweeps, beta, tol=0.0, nthreads=None, tiles=None):
-        """MART in the order views > tile colours > tiles > classes > rays;
-        tiles=None is one tile covering the detector."""
+    def mart(self, csr0: CSR, lattice, P, f0, sweeps, beta, tol=0.0, nthreads=None):
+        """MART in the order views > lattice classes > rays of the class
+        (ascending ray index), from the reference rows rotated to each view."""
         P = np.ascontiguousarray(P, dtype=np.float64).ravel()
         f = np.array(f0, dtype=np.float64, copy=True).ravel()
         done = C.c_int(0)
-        Tu, Tv = tiles if tiles is not None else (self.w.det_u, self.w.det_v)
         rc = self.lib.orc_mart(self._h, _ptr(csr0.rowptr), _ptr(np.ascontiguousarray(csr0.cells)),
                                _ptr(np.ascontiguousarray(csr0.lens)), int(lattice[0]), int(lattice[1]),
-                               int(Tu), int(Tv), _ptr(P), _ptr(f), int(sweeps), float(beta), float(tol),
+                               _ptr(P), _ptr(f), int(sweeps), float(beta), float(tol),
                                C.byref(done), int(nthreads if nthreads is not None else self.nthreads))
         if rc != 0:
             raise ValueError(f"orc_mart failed ({rc})")
@@ -318,13 +312,11 @@ class Oracle:
         return f, seg, lat
 
     # -- whole pipeline -----------------------------------------------------
-    def reconstruct(self, P, sweeps=None, beta=None, f0=None, lattice=None, tiles=None):
+    def reconstruct(self, P, sweeps=None, beta=None, f0=None, lattice=None):
         w = self.w
         csr0 = self.trace_view(0)
         lat = lattice or self.colour(csr0)
-        if tiles is not None and not self.tiles_ok(csr0, tiles):
-            raise ValueError("tiles of one colour would share cells")
         f0 = np.ones(self.n_cells) if f0 is None else f0
         f = self.mart(csr0, lat, P, f0, w.sweeps if sweeps is None else sweeps,
-                      w.beta if beta is None else beta, tiles=tiles)
+                      w.beta if beta is None else beta)
         return f, csr0, lat

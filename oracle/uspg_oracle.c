@@ -600,87 +600,55 @@ void orc_mart_ray(const int64_t *ids, const double *a, int64_t n, double P, doub
         f[ids[j]] *= 1.0 - beta * (a[j] / amax) * (1.0 - rho);
 }
 
-/* Detector tiles of Tu x Tv pixels, coloured in a 2 x 2 checkerboard:
- * colour (tv mod 2) 2 + (tu mod 2) of tile (tu, tv).  Two tiles of one colour
- * are at least one tile apart, so their rays share no cell when every conflict
- * offset has du <= Tu and dw <= Tv.  Returns 0 if the tiling is valid. */
-int orc_tiles_ok(void *h, const uint8_t *mark, int Tu, int Tv)
-{
-    orc_t *o = (orc_t *)h;
-    if (Tu <= 0 || Tv <= 0) return ORC_E_ARG;
-    for (int dw = 0; dw < o->V; ++dw)
-        for (int du = 0; du < o->U; ++du)
-            if (mark[(int64_t)dw * o->U + du] && ((du > Tu && Tu < o->U) || (dw > Tv && Tv < o->V)))
-                return ORC_E_ARG;
-    return ORC_OK;
-}
-
-/* MART over `sweeps` sweeps in this ray order: views ascending (Alg. 1 step
- * 19); tile colours 0..3; the tiles of the colour in ascending index
- * tv * ntu + tu; inside a tile the colour classes c = 0 .. Ku Kv - 1; the
- * tile's rays of the class in ascending ray index.  With one tile covering the
- * detector (Tu >= U, Tv >= V) this is simply views, then classes, then rays.
- * Tiles of one colour share no cell (checked by orc_tiles_ok) and rays of one
- * class share no cell, so the optional thread parallelism over the tiles of a
- * colour gives the same result bit for bit.
- * The rows of view v are the reference rows with every sector index rotated
- * (the stored coefficients are reused for all views).  With tol > 0 the
- * sweeps stop once max_j |f_new - f_old| / f_old <= tol (eq. 19). */
+/* MART over `sweeps` sweeps in the order: views ascending (Alg. 1 loops
+ * over the projections), then the lattice classes c = (w mod Kv) Ku +
+ * (u mod Ku) ascending, then the rays of the class by ascending index
+ * r = w U + u, each ray applied with orc_mart_ray.  The rows of view v are
+ * the reference rows with every sector index rotated by v n_g(i) / q (the
+ * stored coefficients are reused for all views, Sec. III.C).  The rays of one
+ * class share no cell, so spreading them over `nthreads` OpenMP threads gives
+ * the same image bit for bit as one thread.  With tol > 0 the sweeps stop
+ * after the first sweep with max_j |f_new - f_old| / f_old <= tol (eq. 19). */
 int orc_mart(void *h, const int64_t *rowptr, const int64_t *cells, const double *lens,
-             int Ku, int Kv, int Tu, int Tv, const double *P, double *f, int sweeps, double beta,
+             int Ku, int Kv, const double *P, double *f, int sweeps, double beta,
              double tol, int *done, int nthreads)
 {
     orc_t *o = (orc_t *)h;
     int q;
     if (view_group(o, &q) != ORC_OK) return ORC_E_SHIFT;
-    if (Ku <= 0 || Kv <= 0 || Tu <= 0 || Tv <= 0 || sweeps < 0) return ORC_E_ARG;
-    if (Tu > o->U) Tu = o->U;
-    if (Tv > o->V) Tv = o->V;
-    int64_t nrays = (int64_t)o->U * o->V, ncell = o->c2d * o->nz;
-    int64_t nnz = rowptr[nrays];
+    if (Ku <= 0 || Kv <= 0 || sweeps < 0) return ORC_E_ARG;
+    const int64_t U = o->U, V = o->V, nrays = U * V, ncell = o->c2d * o->nz;
+    const int64_t nnz = rowptr[nrays];
     int *ck = (int *)malloc(sizeof(int) * (nnz > 0 ? nnz : 1));
     int *ci = (int *)malloc(sizeof(int) * (nnz > 0 ? nnz : 1));
     int *cs = (int *)malloc(sizeof(int) * (nnz > 0 ? nnz : 1));
     for (int64_t j = 0; j < nnz; ++j) split_cell(o, cells[j], &ck[j], &ci[j], &cs[j]);
     double *fold = tol > 0 ? (double *)malloc(sizeof(double) * ncell) : NULL;
-    int nth = nthreads > 0 ? nthreads : 1;
+    const int nth = nthreads > 0 ? nthreads : 1;
     int maxrow = 0;
     for (int64_t r = 0; r < nrays; ++r)
         if (rowptr[r + 1] - rowptr[r] > maxrow) maxrow = (int)(rowptr[r + 1] - rowptr[r]);
-    const int K = Ku * Kv;
-    const int ntu = (o->U + Tu - 1) / Tu, ntv = (o->V + Tv - 1) / Tv;
     int s_done = 0;
     for (int sw = 0; sw < sweeps; ++sw) {
         if (fold) memcpy(fold, f, sizeof(double) * ncell);
         for (int v = 0; v < o->p; ++v) {
             const double *Pv = P + (int64_t)v * nrays;
-            for (int colour = 0; colour < 4; ++colour) {
+            for (int c = 0; c < Ku * Kv; ++c) {
+                const int64_t cu = c % Ku, cw = c / Ku;
+                const int64_t nu = (U - cu + Ku - 1) / Ku, nw = (V - cw + Kv - 1) / Kv;
 #pragma omp parallel num_threads(nth)
                 {
                     int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * (maxrow > 0 ? maxrow : 1));
-#pragma omp for schedule(dynamic, 1)
-                    for (int64_t t = 0; t < (int64_t)ntu * ntv; ++t) {
-                        int tu = (int)(t % ntu), tv = (int)(t / ntu);
-                        if ((tv % 2) * 2 + (tu % 2) != colour) continue;
-                        int u0 = tu * Tu, w0 = tv * Tv;
-                        int u1 = u0 + Tu < o->U ? u0 + Tu : o->U, w1 = w0 + Tv < o->V ? w0 + Tv : o->V;
-                        for (int c = 0; c < K; ++c) {
-                            int cu = c % Ku, cw = c / Ku;
-                            for (int w = w0; w < w1; ++w) {
-                                if (w % Kv != cw) continue;
-                                for (int u = u0; u < u1; ++u) {
-                                    if (u % Ku != cu) continue;
-                                    int64_t r = (int64_t)w * o->U + u;
-                                    int64_t b = rowptr[r], n = rowptr[r + 1] - b;
-                                    for (int64_t j = 0; j < n; ++j) {
-                                        int i = ci[b + j];
-                                        int sh = (int)(((int64_t)v * (o->ng[i] / q)) % o->ng[i]);
-                                        ids[j] = (int64_t)ck[b + j] * o->c2d + o->head[i] + (cs[b + j] + sh) % o->ng[i];
-                                    }
-                                    orc_mart_ray(ids, lens + b, n, Pv[r], f, beta);
-                                }
-                            }
+#pragma omp for schedule(dynamic, 64)
+                    for (int64_t x = 0; x < nu * nw; ++x) {
+                        const int64_t r = (cw + (x / nu) * Kv) * U + cu + (x % nu) * Ku;
+                        const int64_t b = rowptr[r], n = rowptr[r + 1] - b;
+                        for (int64_t j = 0; j < n; ++j) {
+                            const int i = ci[b + j];
+                            const int sh = (int)(((int64_t)v * (o->ng[i] / q)) % o->ng[i]);
+                            ids[j] = (int64_t)ck[b + j] * o->c2d + o->head[i] + (cs[b + j] + sh) % o->ng[i];
                         }
+                        orc_mart_ray(ids, lens + b, n, Pv[r], f, beta);
                     }
                     free(ids);
                 }

@@ -218,6 +218,9 @@ def test_class_order_contract_non_square_detector():
                     o.mart_ray(ids, a, P[v].ravel()[r], f_ref, 0.3)
     f = o.mart(csr, (ku, kv), P, np.ones(o.n_cells), 2, 0.3)
     assert np.array_equal(f, f_ref)
+    # the rays of a class share no cell: spreading them over threads keeps the bits
+    f4 = o.mart(csr, (ku, kv), P, np.ones(o.n_cells), 2, 0.3, nthreads=4)
+    assert np.array_equal(f4, f_ref)
 
 
 @pytest.mark.parametrize("seed", [0, 1])
@@ -255,62 +258,3 @@ def test_rays_of_a_class_commute(seed):
                 ids, a = rv.row(int(r))
                 o.mart_ray(ids, a, P[v].ravel()[int(r)], g, 0.3)
     assert not np.array_equal(g, f_ref)
-
-
-def _replay_tiled(o, csr, lattice, tiles, P, f, beta, sweeps):
-    """The order views > tile colours > tiles > classes > rays, ray by ray."""
-    w = o.w
-    U, V = w.det_u, w.det_v
-    ku, kv = lattice
-    Tu, Tv = tiles
-    ntu, ntv = -(-U // Tu), -(-V // Tv)
-    for _ in range(sweeps):
-        for v in range(w.n_views):
-            rv = o.rotate(csr, v)
-            for colour in range(4):
-                for t in range(ntu * ntv):
-                    tu, tv = t % ntu, t // ntu
-                    if (tv % 2) * 2 + tu % 2 != colour:
-                        continue
-                    for c in range(ku * kv):
-                        for wv in range(tv * Tv, min(V, (tv + 1) * Tv)):
-                            for u in range(tu * Tu, min(U, (tu + 1) * Tu)):
-                                if (wv % kv) * ku + u % ku != c:
-                                    continue
-                                r = wv * U + u
-                                ids, a = rv.row(r)
-                                o.mart_ray(ids, a, P[v].ravel()[r], f, beta)
-    return f
-
-
-def test_tile_order_contract_and_validity():
-    w = synth.small_cone("rect", n_rings=8, n_views=4, det=14, m=4, n_slices=6).with_(det_v=10)
-    o = Oracle(w)
-    csr = o.trace_view(0)
-    lat = o.colour(csr)
-    mark = o.conflict_offsets(csr)
-    dws, dus = np.nonzero(mark)
-    # smallest valid tiles cover the largest conflict offsets
-    tiles = (int(dus.max()), int(dws.max()))
-    assert o.tiles_ok(csr, tiles)
-    assert not o.tiles_ok(csr, (tiles[0] - 1, tiles[1])) or tiles[0] == 1
-    # same-colour tiles are cell disjoint (checked directly)
-    Tu, Tv = tiles
-    ntu = -(-w.det_u // Tu)
-    owner = {}
-    for r in range(o.n_rays):
-        u, wv = r % w.det_u, r // w.det_u
-        tile = (wv // Tv) * ntu + u // Tu
-        colour = ((wv // Tv) % 2) * 2 + (u // Tu) % 2
-        for c in csr.row(r)[0]:
-            key = (int(c), colour)
-            assert owner.setdefault(key, tile) == tile
-    P = synth.make_projections(w)
-    f_ref = _replay_tiled(o, csr, lat, tiles, P, np.ones(o.n_cells), 0.3, 2)
-    f1 = o.mart(csr, lat, P, np.ones(o.n_cells), 2, 0.3, tiles=tiles)
-    f4 = o.mart(csr, lat, P, np.ones(o.n_cells), 2, 0.3, tiles=tiles, nthreads=4)
-    assert np.array_equal(f1, f_ref) and np.array_equal(f4, f_ref)
-    # one tile covering the detector is the plain class order
-    g = o.mart(csr, lat, P, np.ones(o.n_cells), 2, 0.3)
-    h = o.mart(csr, lat, P, np.ones(o.n_cells), 2, 0.3, tiles=(w.det_u, w.det_v))
-    assert np.array_equal(g, h)
