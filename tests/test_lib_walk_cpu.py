@@ -106,7 +106,7 @@ def test_walk_equals_oracle_all_views(hw, name):
         for r in range(o.n_rays):
             ids, lens = rows[r]
             c2, l2 = direct.row(r)
-            compare_rows(o, r, wk.to_paper(ids, v), lens, c2, l2)
+            compare_rows(o, r, wk.to_paper(ids, v), lens, c2, l2, view=v)
 
 
 @pytest.mark.parametrize("name,step", [("cone-128r-16v", 331), ("cone-256r-32v-hc", 2609)])
