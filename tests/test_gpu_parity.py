@@ -64,7 +64,8 @@ def _cmp_rows(co, o, views, rays, tol_rel):
             c1, l1 = co.row(v, int(r))
             S, D = o.ray(v, int(r))
             c2, l2 = o.trace_line(S, D)
-            compare_rows(o, int(r), c1, l1, c2, l2, rtol=tol_rel, atol=1e-10 if tol_rel < 1e-8 else 1e-7)
+            compare_rows(o, int(r), c1, l1, c2, l2, rtol=tol_rel, atol=1e-10 if tol_rel < 1e-8 else 1e-7,
+                         view=v)
 
 
 def test_rows_equal_oracle_2d(U):
@@ -249,3 +250,29 @@ def test_error_paths(U):
         U.mart(co, proj, img, 1, -0.5)
     with pytest.raises(U.USPGError):
         U.mart(co, proj, img, 1, 0.1, work=torch.empty(16, dtype=torch.uint8, device=dev()))
+
+
+def test_cone256_full_size_20_sweeps_against_golden(U):
+    # the high-contrast 256-ring workload after its full 20 FP32 sweeps
+    # (Sec. III.D, eqs. 17-18) against the FP64 oracle's image of the same
+    # inputs, stored by tests/golden/make_cone256_golden.py (oracle and input
+    # generators only): every cell around the three dense inclusions, every
+    # 997th cell, and max |f| over all cells
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "cone256_sweeps20.npz"))
+    w = synth.get(str(gold["workload"]))
+    assert w.sweeps == int(gold["sweeps"]) and w.beta == float(gold["beta"])
+    P = synth.make_projections(w)
+    f32, grid, co, done = gpu_solve(U, w, P, torch.float32)
+    assert done == w.sweeps
+    assert grid.n_cells == int(gold["n_cells"]) and co.nnz == int(gold["nnz"])
+    assert tuple(co.lattice) == tuple(int(x) for x in gold["lattice"])
+    cells, ref, max_ref = gold["cells"], gold["values"], float(gold["max_abs"])
+    d = np.abs(f32[cells] - ref)
+    err = float(d.max()) / max_ref
+    err_local = float(d.max()) / float(np.abs(ref).max())
+    err_max = abs(float(np.abs(f32).max()) - max_ref) / max_ref
+    print(f"cone-256r-32v-hc 20 sweeps fp32: err_inf={err:.3e} over {len(cells)} cells "
+          f"(against the sampled max {err_local:.3e}), max|f| rel diff {err_max:.3e}, min f {f32.min():.3e}")
+    assert err <= TOL32
+    assert err_max <= TOL32
+    assert f32.min() > 0
