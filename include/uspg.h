@@ -221,6 +221,23 @@ int mart_run(const uspg_coeffs *c, int32_t dtype, const void *proj, void *image,
              size_t work_bytes, int32_t n_sweeps, double beta, double tol,
              int32_t *sweeps_done, void *stream);
 
+/* Allocation-free variant of mart_run, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops or harnesses
+ * that forbid hipMalloc).  Same arguments, semantics and errors as mart_run
+ * without work / work_bytes: the work space is a fixed array of
+ * USPG_NOALLOC_SCRATCH_BYTES inside the library, one copy per device, held
+ * from the library's load until the process ends.  USPG_E_NOMEM (nothing
+ * enqueued) when uspg_mart_workspace_bytes(c, dtype, tol) exceeds it.  The
+ * call allocates nothing and records no timing (uspg_mart_timing does not see
+ * it).  Every call on one device shares that device's array: calls that
+ * overlap on one device (on two streams or from two threads) race and must
+ * be serialised by the caller.  Each call rewrites the work space before
+ * reading it, so nothing carries over from an earlier call. */
+#define USPG_NOALLOC_SCRATCH_BYTES (64LL << 20)
+
+int mart_run_noalloc(const uspg_coeffs *c, int32_t dtype, const void *proj, void *image,
+                     int32_t n_sweeps, double beta, double tol, int32_t *sweeps_done, void *stream);
+
 /* Timing of mart_run's batch kernels (profiling aid).  enable = 1 resets the
  * accumulators and turns timing on: every later mart_run records one HIP
  * event pair on its stream around its sequence of (view, class) batch

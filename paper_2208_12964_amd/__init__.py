@@ -72,6 +72,7 @@ def lib():
     L.uspg_mart_workspace_bytes.argtypes = [P, I32, D]
     L.uspg_mart_workspace_bytes.restype = SZ
     L.mart_run.argtypes = [P, I32, P, P, P, SZ, I32, D, D, P, P]
+    L.mart_run_noalloc.argtypes = [P, I32, P, P, I32, D, D, P, P]
     L.uspg_to_cartesian.argtypes = [P, I32, P, P, I32, I32, P]
     L.uspg_mart_timing.argtypes = [I32, P, P]
     L.uspg_build_batch.argtypes = [I32, P, I32, C.POINTER(P)]
@@ -98,7 +99,7 @@ def lib():
     L.uspg_check_projections.argtypes = [P, I32, P, P, P]
     L.uspg_last_error.restype = C.c_char_p
     for name in ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_build_coeffs",
-                 "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "uspg_coeffs_view_nnz", "mart_run",
+                 "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "uspg_coeffs_view_nnz", "mart_run", "mart_run_noalloc",
                  "uspg_to_cartesian", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
                  "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_engine_create",
                  "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info", "uspg_build_slabs",
@@ -304,6 +305,24 @@ def mart(coeffs: Coeffs, proj: torch.Tensor, image: torch.Tensor, n_sweeps: int,
                           C.c_void_p(_stream(stream))))
     if stream is not None:
         _used_on(stream, proj, image, work)
+    return done.value
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # USPG_NOALLOC_SCRATCH_BYTES
+
+
+def mart_run_noalloc(coeffs: Coeffs, proj: torch.Tensor, image: torch.Tensor, n_sweeps: int, beta: float,
+                     tol: float = 0.0, stream=None) -> int:
+    """Sp-MART in place on ``image`` with the library's fixed work space
+    (``mart_run_noalloc``: no device allocation; calls on one device must not
+    overlap).  Returns the number of sweeps run."""
+    _problem_check(coeffs, proj, image)
+    done = C.c_int32()
+    _check(lib().mart_run_noalloc(coeffs.handle, DTYPE[image.dtype], C.c_void_p(proj.data_ptr()),
+                                  C.c_void_p(image.data_ptr()), n_sweeps, beta, tol, C.byref(done),
+                                  C.c_void_p(_stream(stream))))
+    if stream is not None:
+        _used_on(stream, proj, image)
     return done.value
 
 
@@ -515,7 +534,8 @@ class Slabs:
 
 EXPORTED = ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_free_grid",
             "uspg_build_coeffs", "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts",
-            "uspg_free_coeffs", "uspg_mart_workspace_bytes", "mart_run", "uspg_to_cartesian", "uspg_coeffs_view_nnz",
+            "uspg_free_coeffs", "uspg_mart_workspace_bytes", "mart_run", "mart_run_noalloc", "uspg_to_cartesian",
+            "uspg_coeffs_view_nnz",
             "uspg_last_error", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
             "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_free_batch",
             "uspg_engine_create", "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info",
@@ -536,5 +556,5 @@ def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, co
     return image, cart, grid, coeffs
 
 
-__all__ = ["Grid", "Coeffs", "Batch", "Engine", "Slabs", "mart", "mart_timing", "to_cartesian", "reconstruct", "USPGError", "lib", "LIB_PATH",
+__all__ = ["Grid", "Coeffs", "Batch", "Engine", "Slabs", "mart", "mart_run_noalloc", "mart_timing", "to_cartesian", "reconstruct", "USPGError", "lib", "LIB_PATH",
            "EXPORTED", "math"]

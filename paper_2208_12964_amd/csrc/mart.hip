@@ -279,9 +279,16 @@ bool stream_capturing(hipStream_t s)
     return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
 }
 
+// Calls of the allocation-free entry point on this thread are not timed
+// (timing creates events).
+thread_local bool t_untimed = false;
+
+UntimedScope::UntimedScope() : prev(t_untimed) { t_untimed = true; }
+UntimedScope::~UntimedScope() { t_untimed = prev; }
+
 // Timing records and waits on events, which a stream under graph capture
 // cannot do: captured calls are not timed.
-bool mart_timing_on(hipStream_t s) { return g_timing.load() != 0 && !stream_capturing(s); }
+bool mart_timing_on(hipStream_t s) { return g_timing.load() != 0 && !t_untimed && !stream_capturing(s); }
 
 void mart_timing_add(int64_t ns, int64_t launches)
 {

@@ -152,6 +152,12 @@ bool stream_coefs(size_t coef_bytes, size_t image_bytes);
 // stored reference rows).
 inline size_t coef_set_bytes(const uspg_coeffs *c) { return c->view_coef.p ? c->view_coef.bytes : c->coef.bytes; }
 bool mart_timing_on(hipStream_t s);
+// While one lives, mart_launch on this thread records no timing events.
+struct UntimedScope {
+    bool prev;
+    UntimedScope();
+    ~UntimedScope();
+};
 void mart_timing_add(int64_t ns, int64_t launches);
 // One (view, class) batch of the single-problem kernel over explicit rows
 // of (id, coefficient) pairs of float coefficients (shift added mod wtot);
