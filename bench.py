@@ -23,31 +23,40 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE = os.path.join(ROOT, "profiles", "mart_batch-cone-256r-32v-hc.md")
-# sources of the mart_batch kernel: the kernel, then the per-ray routine
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2208_12964_amd", "csrc", f) for f in ("mart_batch.hpp", "mart_row.hpp")]
+CSRC = os.path.join(ROOT, "paper_2208_12964_amd", "csrc")
+# the batch kernel of each row form, its counter summary and its sources
+# (the kernel, then the headers it includes from this library)
+KERNELS = {
+    "coded": ("mart_coded", ("mart_coded.hpp", "coded_rows.hpp", "trace_walk.hpp", "mart_batch.hpp", "mart_row.hpp")),
+    "stored": ("mart_batch", ("mart_batch.hpp", "mart_row.hpp")),
+}
 
 
-def kernel_sha256() -> str:
+def profile_path(kernel: str, workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{kernel}-{workload}.md")
+
+
+def kernel_sha256(rows: str = "coded") -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SRCS:
-        h.update(open(f, "rb").read())
+    for f in KERNELS[rows][1]:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()
 
 
-def counter_traffic():
-    """HBM bytes per mart_batch launch from the committed rocprofv3 counter
+def counter_traffic(rows: str, workload: str):
+    """HBM bytes per batch-kernel launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
     the kernel source changed since the counters were taken."""
-    if not os.path.exists(PROFILE):
+    path = profile_path(KERNELS[rows][0], workload)
+    if not os.path.exists(path):
         return None
     fields = {}
-    for line in open(PROFILE):
+    for line in open(path):
         if ":" in line and line.startswith("- `"):
             key, val = line[3:].split("`", 1)
             fields[key] = val.split(":", 1)[1].strip().strip("`")
-    if fields.get("source_sha256") != kernel_sha256() or "traffic_bytes_per_launch" not in fields:
+    if fields.get("source_sha256") != kernel_sha256(rows) or "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -64,6 +73,8 @@ def parse():
                          "paper's Table 1 scans with its literal segment scheme and image quality; "
                          "slabs: the same solve split into z-slabs (the multi-device layout) on one GPU")
     ap.add_argument("--slabs", type=int, default=8, help="slabs: number of z-slabs")
+    ap.add_argument("--rows", default="coded", choices=["coded", "stored"],
+                    help="cone-beam rows: coded (rebuilt per column, the default) or stored (id, coefficient) pairs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=20, help="detector rows in the oracle sample")
     ap.add_argument("--sweeps", type=int, default=0, help="override the sweep count (profiling runs)")
@@ -489,7 +500,7 @@ def main():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
         grid = U.Grid.from_workload(w)
-        co = U.Coeffs.from_workload(grid, w, torch.float32)
+        co = U.Coeffs.from_workload(grid, w, torch.float32, rows=args.rows)
         ev[1].record(stream)
         img = torch.ones(grid.n_cells, dtype=torch.float32, device=dev)
         U.mart(co, proj, img, w.sweeps, w.beta)
@@ -497,7 +508,7 @@ def main():
         cart = U.to_cartesian(grid, img, nc)
         ev[3].record(stream)
         if record is not None:
-            record.append((ev, co.nnz, co.lattice, co.max_row))
+            record.append((ev, co.nnz, co.lattice, co.max_row, co.coded, co.explicit_rays))
         return img, cart, co, grid
 
     for _ in range(args.warmup):
@@ -523,7 +534,8 @@ def main():
     per_launch_s = batch_ms * 1e-3 / batch_launches
     bytes_per_launch = 16.0 * updates / n_launch
     achieved = bytes_per_launch / per_launch_s / 1e9
-    traffic = counter_traffic()
+    kernel = KERNELS["coded" if rec[0][4] else "stored"][0]
+    traffic = counter_traffic("coded" if rec[0][4] else "stored", w.name)
     copy_gbs = copy_bandwidth(dev)
     f = img.float().cpu().numpy()
     out = {
@@ -533,7 +545,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "rings": w.n_rings, "slices": w.n_slices, "views": w.n_views,
                    "detector": f"{w.det_u}x{w.det_v}", "sweeps": w.sweeps, "beta": w.beta,
-                   "nnz_ref": nnz, "lattice": list(lattice), "remap": f"{nc}x{nc}x{w.n_slices}"},
+                   "nnz_ref": nnz, "lattice": list(lattice), "remap": f"{nc}x{nc}x{w.n_slices}",
+                   "rows": "coded" if rec[0][4] else "stored", "explicit_rays": rec[0][5]},
         "sweeps_per_s": w.sweeps / (mart_ms * 1e-3),
         "phases_ms": {"build": build_ms, "mart": mart_ms, "remap": remap_ms},
         "mart_ms_over_steps": {"median": float(np.median(mart_each)), "min": float(np.min(mart_each)),
@@ -541,7 +554,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "mart_batch", "bytes_per_update": 16,
+                     "kernel": kernel, "bytes_per_update": 16,
                      "launches_per_step": n_launch, "avg_launch_us": per_launch_s * 1e6,
                      "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None},
         "image": {"min": float(f.min()), "max": float(f.max())},

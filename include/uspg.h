@@ -150,7 +150,19 @@ typedef struct {
     int32_t colour_u, colour_v;
     int32_t quarter;        /* SEGMENTS only: 1 traces one detector quadrant and mirrors it */
     int32_t view_rows;      /* SEGMENTS only: 0 keeps every view's rows when they fit, 1 re-bins per view */
+    int32_t row_codes;      /* CONE_3D LENGTH / BINARY: 0 codes the rows (see below), 1 stored rows only */
 } uspg_scan_desc;
+
+/* row_codes (CONE_3D with LENGTH or BINARY weights, else ignored): the rays
+ * of one detector column share their in-plane path, so with 0 the library
+ * also keeps, per column, that path's sector pieces (ray parameter of each
+ * piece's start, FP64, and its slice-0 cell; 12 bytes per piece) and, per
+ * ray, a 48-byte header plus two bits per entry (next piece, next slice).
+ * mart_run then rebuilds every entry from these instead of reading the
+ * stored (cell, coefficient) pairs; each rebuilt entry is checked against
+ * the stored one when the codes are built, and rays that do not match bit
+ * for bit (none on the configured cone-beam scans) keep their stored rows.
+ * The solve gives the same bits either way.  1 builds the stored rows only. */
 
 /* Largest size of the kept per-view rows of SEGMENTS coefficients. */
 #define USPG_VIEW_ROWS_MAX_BYTES (8LL << 30)
@@ -169,6 +181,13 @@ int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *scan, void *stre
 int uspg_coeffs_info(const uspg_coeffs *c, int64_t *nnz_ref, int64_t *n_rays,
                      int32_t *colour_u, int32_t *colour_v, int32_t *max_row,
                      int64_t *device_bytes);
+
+/* Coded rows of a coefficient set (row_codes above): *coded = 1 when
+ * mart_run reads them, the rays coded and left explicit (rays that miss the
+ * cylinder count in neither) and the device bytes of the codes.  NULL
+ * skips. */
+int uspg_coeffs_code_info(const uspg_coeffs *c, int32_t *coded, int64_t *coded_rays, int64_t *explicit_rays,
+                          int64_t *code_bytes);
 
 /* Host copy of the row of ray `ray` in view `view` (cells in the paper's
  * numbering, rotated to that view; lengths as stored; with SEGMENTS the

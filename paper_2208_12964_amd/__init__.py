@@ -42,7 +42,8 @@ class _ScanDesc(C.Structure):
                 ("det_u", C.c_int32), ("det_v", C.c_int32), ("det_half_u", C.c_double),
                 ("det_half_v", C.c_double), ("src_axis", C.c_double), ("src_det", C.c_double),
                 ("weights", C.c_int32), ("coeff_dtype", C.c_int32), ("colour_u", C.c_int32),
-                ("colour_v", C.c_int32), ("quarter", C.c_int32), ("view_rows", C.c_int32)]
+                ("colour_v", C.c_int32), ("quarter", C.c_int32), ("view_rows", C.c_int32),
+                ("row_codes", C.c_int32)]
 
 
 _lib = None
@@ -67,6 +68,7 @@ def lib():
     L.uspg_coeffs_row.argtypes = [P, I32, I64, P, P, I32, P]
     L.uspg_coeffs_conflicts.argtypes = [P, P]
     L.uspg_coeffs_view_nnz.argtypes = [P, P]
+    L.uspg_coeffs_code_info.argtypes = [P, P, P, P, P]
     L.uspg_free_coeffs.argtypes = [P]
     L.uspg_free_coeffs.restype = None
     L.uspg_mart_workspace_bytes.argtypes = [P, I32, D]
@@ -99,7 +101,7 @@ def lib():
     L.uspg_check_projections.argtypes = [P, I32, P, P, P]
     L.uspg_last_error.restype = C.c_char_p
     for name in ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_build_coeffs",
-                 "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "uspg_coeffs_view_nnz", "mart_run", "mart_run_noalloc",
+                 "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts", "uspg_coeffs_view_nnz", "uspg_coeffs_code_info", "mart_run", "mart_run_noalloc",
                  "uspg_to_cartesian", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
                  "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_engine_create",
                  "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info", "uspg_build_slabs",
@@ -171,12 +173,13 @@ class Coeffs:
     def __init__(self, grid: Grid, geometry: str, n_views: int, span: float, det_u: int, det_v: int = 1,
                  det_half_u: float = 1.0, det_half_v: float = 0.0, src_axis: float = 0.0,
                  src_det: float = 0.0, weights: str = "length", coeff_dtype=torch.float32,
-                 colour=(0, 0), stream=None, quarter: bool = False, view_rows: str = "keep"):
+                 colour=(0, 0), stream=None, quarter: bool = False, view_rows: str = "keep",
+                 rows: str = "coded"):
         L = lib()
         self.grid = grid
         d = _ScanDesc(GEOMETRY[geometry], n_views, span, det_u, det_v, det_half_u, det_half_v,
                       src_axis, src_det, WEIGHTS[weights], DTYPE[coeff_dtype], colour[0], colour[1],
-                      1 if quarter else 0, {"keep": 0, "rebin": 1}[view_rows])
+                      1 if quarter else 0, {"keep": 0, "rebin": 1}[view_rows], {"coded": 0, "stored": 1}[rows])
         h = C.c_void_p()
         _check(L.uspg_build_coeffs(grid.handle, C.byref(d), C.c_void_p(_stream(stream)), C.byref(h)))
         self.handle = h
@@ -188,14 +191,17 @@ class Coeffs:
         self.nnz, self.n_rays = nnz.value, nr.value
         self.lattice = (ku.value, kv.value)
         self.max_row, self.device_bytes = mr.value, db.value
+        cd, ncr, nxr, cb = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(L.uspg_coeffs_code_info(h, C.byref(cd), C.byref(ncr), C.byref(nxr), C.byref(cb)))
+        self.coded, self.coded_rays, self.explicit_rays, self.code_bytes = bool(cd.value), ncr.value, nxr.value, cb.value
 
     @classmethod
     def from_workload(cls, grid: Grid, w, coeff_dtype=torch.float32, colour=(0, 0), stream=None,
-                      view_rows: str = "keep"):
+                      view_rows: str = "keep", rows: str = "coded"):
         weights = "segments" if w.rebin else ("binary" if w.binary else "length")
         return cls(grid, w.geometry, w.n_views, w.span, w.det_u, w.det_v, w.det_half_u, w.det_half_v,
                    w.src_axis, w.src_det, weights, coeff_dtype, colour, stream, quarter=w.quarter,
-                   view_rows=view_rows)
+                   view_rows=view_rows, rows=rows)
 
     def row(self, view: int, ray: int):
         import numpy as np
@@ -535,7 +541,7 @@ class Slabs:
 EXPORTED = ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_free_grid",
             "uspg_build_coeffs", "uspg_coeffs_info", "uspg_coeffs_row", "uspg_coeffs_conflicts",
             "uspg_free_coeffs", "uspg_mart_workspace_bytes", "mart_run", "mart_run_noalloc", "uspg_to_cartesian",
-            "uspg_coeffs_view_nnz",
+            "uspg_coeffs_view_nnz", "uspg_coeffs_code_info",
             "uspg_last_error", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
             "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_free_batch",
             "uspg_engine_create", "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info",

@@ -184,6 +184,7 @@ int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *sc, void *stream
         sc->weights != USPG_WEIGHTS_SEGMENTS)
         return fail(USPG_E_ARG, "weights");
     if (sc->coeff_dtype != USPG_F32 && sc->coeff_dtype != USPG_F64) return fail(USPG_E_ARG, "coeff_dtype");
+    if (sc->row_codes != 0 && sc->row_codes != 1) return fail(USPG_E_ARG, "row_codes must be 0 or 1");
     if ((int64_t)sc->det_u * sc->det_v >= (int64_t)1 << 31) return fail(USPG_E_ARG, "too many rays");
     hipStream_t s = (hipStream_t)stream;
     if (sc->weights == USPG_WEIGHTS_SEGMENTS) {
@@ -252,8 +253,13 @@ int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *sc, void *stream
         uspg_free_coeffs(c);
         return rc;
     }
+    if (cone && sc->row_codes == 0 && (rc = build_row_codes(c, s)) != USPG_OK) {
+        uspg_free_coeffs(c);
+        return rc;
+    }
     c->device_bytes = (int64_t)(c->rowptr.bytes + c->coef.bytes + c->d_kq.bytes +
-                                c->d_hq.bytes + c->d_ring_of_off.bytes);
+                                c->d_hq.bytes + c->d_ring_of_off.bytes + c->d_colptr.bytes + c->d_colt.bytes +
+                                c->d_colid.bytes + c->d_codes.bytes + c->d_words.bytes);
     *out = c;
     return USPG_OK;
 }
@@ -322,6 +328,19 @@ int uspg_coeffs_row(const uspg_coeffs *c, int32_t view, int64_t ray, int64_t *ce
     return USPG_OK;
 }
 
+int uspg_coeffs_code_info(const uspg_coeffs *c, int32_t *coded, int64_t *coded_rays, int64_t *explicit_rays,
+                          int64_t *code_bytes)
+{
+    if (!c) return fail(USPG_E_ARG, "null coefficients");
+    if (coded) *coded = c->coded ? 1 : 0;
+    if (coded_rays) *coded_rays = c->coded_rays;
+    if (explicit_rays) *explicit_rays = c->explicit_rays;
+    if (code_bytes)
+        *code_bytes = (int64_t)(c->d_colptr.bytes + c->d_colt.bytes + c->d_colid.bytes + c->d_codes.bytes +
+                                c->d_words.bytes);
+    return USPG_OK;
+}
+
 int uspg_coeffs_view_nnz(const uspg_coeffs *c, int64_t *nnz_per_view)
 {
     if (!c || !nnz_per_view) return fail(USPG_E_ARG, "null argument");
@@ -353,6 +372,11 @@ void uspg_free_coeffs(uspg_coeffs *c)
     c->view_rowptr.release();
     c->view_coef.release();
     c->d_view_start.release();
+    c->d_colptr.release();
+    c->d_colt.release();
+    c->d_colid.release();
+    c->d_codes.release();
+    c->d_words.release();
     delete c;
 }
 

@@ -18,6 +18,7 @@
 #include <atomic>
 
 #include "mart_batch.hpp"
+#include "mart_coded.hpp"
 #include "mart_row.hpp"
 #include "uspg_internal.hpp"
 
@@ -32,7 +33,10 @@ using row::wave_max;
 using row::wave_sum;
 
 using batchk::BatchArgs;
+using batchk::CodedArgs;
 using batchk::mart_batch;
+using batchk::mart_coded;
+using batchk::mart_explicit;
 constexpr int kWaves = batchk::kWaves;
 constexpr int kBlock = batchk::kBlock;
 // Grid cap of the batch kernel, in workgroups per compute unit: measured on
@@ -120,6 +124,67 @@ void launch_batch_n(int nch, bool nt, const BatchArgs<T, TC> &A, hipStream_t s)
     else launch_batch_nch<T, TC, false>(nch, A, s);
 }
 
+// Coded rows: the instantiation bounds the register path (coded rows have
+// at most 16 chunks); the explicit rows of a set, if any, run in a second
+// launch per batch with the stored-row cache rule.
+template <class T, class TC>
+void launch_coded(int nch, const CodedArgs<T, TC> &A, hipStream_t s)
+{
+    if (nch <= 2) hipLaunchKernelGGL((mart_coded<T, TC, 2>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
+    else if (nch <= 4) hipLaunchKernelGGL((mart_coded<T, TC, 4>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
+    else if (nch <= 8) hipLaunchKernelGGL((mart_coded<T, TC, 8>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
+    else if (nch <= 12) hipLaunchKernelGGL((mart_coded<T, TC, 12>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
+    else hipLaunchKernelGGL((mart_coded<T, TC, 16>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
+}
+
+template <class T, class TC, bool NT>
+void launch_explicit(int nch, const CodedArgs<T, TC> &A, hipStream_t s)
+{
+    if (nch <= 4) hipLaunchKernelGGL((mart_explicit<T, TC, 4, NT>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
+    else if (nch <= 16) hipLaunchKernelGGL((mart_explicit<T, TC, 16, NT>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
+    else hipLaunchKernelGGL((mart_explicit<T, TC, 32, NT>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
+}
+
+// Ray order of the coded kernel inside a class: bands of 8 class rows,
+// w fastest inside a band, so that the rays in flight on one XCD share
+// their columns' in-plane paths (cache-resident) while neighbouring columns
+// still share image lines.  Measured on the 256-ring cone (us per batch):
+// band 1 (row order) 103, 2: 104, 4: 100, 8: 98, 16: 106, 32: 125, the
+// whole class column-major 155.
+constexpr int kCodedBand = 8;
+
+template <class T, class TC>
+CodedArgs<T, TC> coded_args(const uspg_coeffs *c, const BatchArgs<T, TC> &B)
+{
+    CodedArgs<T, TC> A{};
+    A.B = B;
+    A.codes = c->d_codes.as<coded::RayCode>();
+    A.words = c->d_words.as<uint64_t>();
+    A.t = c->d_colt.as<double>();
+    A.id0 = c->d_colid.as<uint32_t>();
+    A.Q = coded::CodeGeo{c->g->z0, c->g->h, c->g->nz, (uint32_t)c->Cq, (uint32_t)c->Wc};
+    A.binary = c->scan.weights == USPG_WEIGHTS_BINARY;
+    A.band = kCodedBand;
+    return A;
+}
+
+// One (view, class) batch of a single problem: the coded kernel when the
+// coefficient set has coded rows, else the stored-row kernel.
+template <class T, class TC>
+void launch_step(const uspg_coeffs *c, int nch, bool nt, const BatchArgs<T, TC> &B, hipStream_t s)
+{
+    if (c->coded) {
+        const CodedArgs<T, TC> A = coded_args<T, TC>(c, B);
+        launch_coded<T, TC>(std::min(nch, 16), A, s);
+        if (c->explicit_rays > 0) {
+            if (nt) launch_explicit<T, TC, true>(nch, A, s);
+            else launch_explicit<T, TC, false>(nch, A, s);
+        }
+    } else {
+        launch_batch_n<T, TC>(nch, nt, B, s);
+    }
+}
+
 int pick_nch(int max_row) { return (max_row + 63) / 64; }
 
 // Coefficient loads take the non-temporal hint unless the coefficient set and
@@ -202,7 +267,7 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
             for (int cl = 0; cl < K; ++cl) {
                 const BatchArgs<T, TC> A = batch_args<T, TC>(c, proj, nat, beta, v, cl);
                 if (A.ncls == 0) continue;
-                launch_batch_n<T, TC>(nch, nt, A, s);
+                launch_step<T, TC>(c, nch, nt, A, s);
                 ++launches;
             }
         }
@@ -364,18 +429,18 @@ int batch_step(const uspg_coeffs *c, int dtype, const void *proj, void *f, doubl
     if (dtype == USPG_F64) {
         if (cf64) {
             const auto A = batch_args<double, double>(c, (const double *)proj, (double *)f, beta, v, cl);
-            if (A.ncls) launch_batch_n<double, double>(nch, nt, A, s);
+            if (A.ncls) launch_step<double, double>(c, nch, nt, A, s);
         } else {
             const auto A = batch_args<double, float>(c, (const double *)proj, (double *)f, beta, v, cl);
-            if (A.ncls) launch_batch_n<double, float>(nch, nt, A, s);
+            if (A.ncls) launch_step<double, float>(c, nch, nt, A, s);
         }
     } else {
         if (cf64) {
             const auto A = batch_args<float, double>(c, (const float *)proj, (float *)f, beta, v, cl);
-            if (A.ncls) launch_batch_n<float, double>(nch, nt, A, s);
+            if (A.ncls) launch_step<float, double>(c, nch, nt, A, s);
         } else {
             const auto A = batch_args<float, float>(c, (const float *)proj, (float *)f, beta, v, cl);
-            if (A.ncls) launch_batch_n<float, float>(nch, nt, A, s);
+            if (A.ncls) launch_step<float, float>(c, nch, nt, A, s);
         }
     }
     return hipGetLastError() == hipSuccess ? USPG_OK : fail(USPG_E_HIP, "batch launch failed");

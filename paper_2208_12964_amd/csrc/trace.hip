@@ -73,7 +73,8 @@ __global__ void row_lengths_max(const uint32_t *cnt, int64_t n, unsigned int *mx
 
 }  // namespace
 
-int trace_reference_view(uspg_coeffs *c, hipStream_t s)
+// Geometry of the view-0 walk of a coefficient set (device tables).
+TraceGeo trace_geo(const uspg_coeffs *c)
 {
     const uspg_grid *g = c->g;
     const uspg_scan_desc &sc = c->scan;
@@ -89,6 +90,13 @@ int trace_reference_view(uspg_coeffs *c, hipStream_t s)
     G.U = sc.det_u; G.V = sc.det_v;
     G.Wu = sc.det_half_u; G.Wv = sc.det_half_v; G.Dso = sc.src_axis; G.Dsd = sc.src_det;
     G.eps = 1e-12 * g->R;
+    return G;
+}
+
+int trace_reference_view(uspg_coeffs *c, hipStream_t s)
+{
+    const uspg_scan_desc &sc = c->scan;
+    const TraceGeo G = trace_geo(c);
 
     const int64_t nrays = c->nrays;
     const unsigned blocks = (unsigned)((nrays + 255) / 256);

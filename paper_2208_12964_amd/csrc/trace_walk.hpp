@@ -133,6 +133,7 @@ struct Entry {
 // Collects a row: counts slots (WRITE = false) or writes them.
 template <bool WRITE, class TC>
 struct RowSink {
+    static constexpr bool kPieces = false;   // takes emitted cell pieces, not whole sector pieces
     int64_t base;          // first output slot of the row
     int64_t count = 0;     // slots reserved so far
     bool pend = false, held = false, armed = false;
@@ -257,22 +258,28 @@ struct Walker {
     }
 
     // Piece [ta, tb] inside one ring and sector, cut at the axial planes.
+    // A sink with kPieces set takes the whole sector piece instead (the
+    // in-plane path of a detector column, whose rays differ only in z).
     USPG_HD void sector_piece(int i, int s, double ta, double tb)
     {
-        double tcur = ta;
-        while (tz < tb) {
-            double t = tz > tcur ? tz : tcur;
-            sink.emit(cell_id(i, s), (t - tcur) * ray.L);
-            tcur = t;
-            k += dk;
-            if (k < 0 || k >= G.nz) {   // guard only: the chord is clipped to the slab
-                k -= dk;
-                tz = INFINITY;
-                break;
+        if constexpr (Sink::kPieces) {
+            sink.piece(cell_id(i, s), ta, tb);
+        } else {
+            double tcur = ta;
+            while (tz < tb) {
+                double t = tz > tcur ? tz : tcur;
+                sink.emit(cell_id(i, s), (t - tcur) * ray.L);
+                tcur = t;
+                k += dk;
+                if (k < 0 || k >= G.nz) {   // guard only: the chord is clipped to the slab
+                    k -= dk;
+                    tz = INFINITY;
+                    break;
+                }
+                next_plane();
             }
-            next_plane();
+            sink.emit(cell_id(i, s), (tb - tcur) * ray.L);
         }
-        sink.emit(cell_id(i, s), (tb - tcur) * ray.L);
     }
 
     USPG_HD int sector_of(int i, double x, double y) const

@@ -105,6 +105,16 @@ struct uspg_coeffs {
     std::vector<int64_t> view_start;
     uspg::DevBuf d_view_start;    // int64 [n_views + 1], device copy of view_start
     int32_t view_max_row = 0;
+    // Coded rows (cone beam, coded_rows.hpp): per detector column its
+    // in-plane path, per ray its code; mart_run reads these instead of the
+    // stored rows (which stay for explicit rays and the other solvers).
+    bool coded = false;
+    int64_t coded_rays = 0, explicit_rays = 0;
+    uspg::DevBuf d_colptr;        // int64 [det_u + 1]: first record of each column
+    uspg::DevBuf d_colt;          // double [records]: piece starts (a column closes with its end)
+    uspg::DevBuf d_colid;         // uint32 [records]: slice-0 cell id of each piece
+    uspg::DevBuf d_codes;         // RayCode [nrays]
+    uspg::DevBuf d_words;         // uint64: piece / slice bits of the coded rays
 };
 
 namespace uspg {
@@ -136,6 +146,8 @@ int choose_lattice(uspg_coeffs *c);
 int segments_reference_view(uspg_coeffs *c, hipStream_t s);
 int colour_segments(uspg_coeffs *c, hipStream_t s);
 int segments_row(const uspg_coeffs *c, int view, int64_t ray, std::vector<int64_t> &cells);
+// coded.hip: coded rows of a cone-beam coefficient set (after tracing)
+int build_row_codes(uspg_coeffs *c, hipStream_t s);
 // scan.hip
 int exclusive_scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, hipStream_t s);
 int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s);

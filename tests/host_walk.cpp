@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <vector>
 
+#include "../paper_2208_12964_amd/csrc/coded_rows.hpp"
 #include "../paper_2208_12964_amd/csrc/trace_walk.hpp"
 
 using namespace uspg::walk;
@@ -16,6 +17,11 @@ struct State {
     std::vector<int64_t> head;
     std::vector<double2> cs;
     TraceGeo G{};
+    // coded rows: column records
+    std::vector<int64_t> colptr;
+    std::vector<double> t;
+    std::vector<uint32_t> id0;
+    int64_t gaps = 0;
 };
 
 State st;
@@ -95,6 +101,82 @@ int hw_trace(int64_t ray, uint32_t *ids, double *lens, int cap)
     Ray r;
     if (!setup_ray(st.G, ray, r)) return 0;
     return walk_row(r, ids, lens, cap);
+}
+
+// Column records of every detector column (coded rows); returns the total.
+int64_t hw_columns()
+{
+    const int U = st.G.U;
+    st.colptr.assign(U + 1, 0);
+    st.gaps = 0;
+    for (int u = 0; u < U; ++u) {
+        uspg::coded::PieceSink cnt;
+        uspg::coded::walk_column(st.G, u, cnt);
+        st.colptr[u + 1] = st.colptr[u] + uspg::coded::column_records(cnt);
+        st.gaps += cnt.gap;
+    }
+    const int64_t m = st.colptr[U];
+    st.t.assign(m, 0.0);
+    st.id0.assign(m, 0);
+    for (int u = 0; u < U; ++u) {
+        uspg::coded::PieceSink fill;
+        fill.base = st.colptr[u];
+        fill.t = st.t.data();
+        fill.id0 = st.id0.data();
+        uspg::coded::walk_column(st.G, u, fill);
+        fill.close();
+    }
+    return m;
+}
+
+int64_t hw_column_gaps() { return st.gaps; }
+
+// Codes ray `ray` from its FP32 stored row and rebuilds the row from the
+// code alone (ids, lens: cap entries).  Returns the row length, -2 when the
+// row is left explicit, -1 on a mismatch of the rebuilt row, -3 if cap is
+// small.  info[0..3] = p0, kinit, planes crossed, mask words.
+int hw_code_ray(int64_t ray, uint32_t *ids, float *lens, int cap, int64_t *info)
+{
+    using namespace uspg::coded;
+    Ray r;
+    if (!setup_ray(st.G, ray, r)) return 0;
+    RowSink<false, float> cnt;
+    cnt.base = 0; cnt.ids = nullptr; cnt.a = nullptr; cnt.binary = false; cnt.eps = st.G.eps;
+    { Walker<RowSink<false, float>> w(st.G, r, cnt); w.run(); }
+    const int n = (int)cnt.count;
+    if (n > cap) return -3;
+    std::vector<uint32_t> sid(n);
+    std::vector<float> sa(n);
+    RowSink<true, float> fill;
+    fill.base = 0; fill.ids = sid.data(); fill.a = sa.data(); fill.binary = false; fill.eps = st.G.eps;
+    { Walker<RowSink<true, float>> w(st.G, r, fill); w.run(); }
+    CodeGeo Q{st.G.z0, st.G.h, st.G.nz, (uint32_t)st.G.Cq, (uint32_t)st.G.Wc};
+    const int u = (int)(ray % st.G.U);
+    RayCode rc{};
+    std::vector<uint64_t> words(2 * ((n + 63) / 64) + 2, 0);
+    auto row = [&](int e, uint32_t &id, float &a) { id = sid[e]; a = sa[e]; };
+    if (!code_ray<float>(Q, st.G, r, st.t.data(), st.id0.data(), st.colptr[u], st.colptr[u + 1] - 1, row, n,
+                         false, rc, words.data()))
+        return -2;
+    // rebuild from the code only, as the kernel does
+    const int dk = code_dk(rc), kinit = code_kinit(rc), J = code_planes(rc);
+    std::vector<double> bounds(J + 2);
+    for (int j = 0; j <= J + 1; ++j) bounds[j] = slice_bound(Q, kinit, dk, J, rc.t0, rc.t1, rc.ez, j);
+    int64_t pacc = rc.p0;
+    int jacc = code_j0(rc);
+    for (int e = 0; e < n; ++e) {
+        if (e > 0) {
+            const uint64_t pwd = words[2 * ((e - 1) >> 6)], kwd = words[2 * ((e - 1) >> 6) + 1];
+            pacc += (pwd >> ((e - 1) & 63)) & 1;
+            jacc += (int)((kwd >> ((e - 1) & 63)) & 1);
+        }
+        const int64_t p = pacc;
+        ids[e] = st.id0[p] + (uint32_t)(kinit + dk * jacc) * Q.Cq;
+        lens[e] = (float)entry_length(st.t[p], st.t[p + 1], bounds[jacc], bounds[jacc + 1], rc.L);
+        if (ids[e] != sid[e] || !(lens[e] == sa[e])) return -1;
+    }
+    info[0] = rc.p0; info[1] = kinit; info[2] = J; info[3] = 2 * ((n + 63) / 64);
+    return n;
 }
 
 // Row of an arbitrary line from S towards D.

@@ -31,6 +31,9 @@ def hw():
     L.hw_trace.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int]
     L.hw_tables.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     L.hw_tables.restype = C.c_int64
+    L.hw_columns.restype = C.c_int64
+    L.hw_column_gaps.restype = C.c_int64
+    L.hw_code_ray.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
     return L
 
 
@@ -175,3 +178,29 @@ def test_layout_group_size_is_a_bijection(hw, grp):
             c2, l2 = o.trace_view(0).row(r) if r == 0 else o.trace_line(*o.ray(0, r))
             compare_rows(o, r, wk.to_paper(ids), lens, c2, l2)
         assert ref.Cq <= wk.Cq
+
+
+@pytest.mark.parametrize("name,step", [("cone-small", 1), ("cone-odd", 1), ("cone-128r-16v", 7),
+                                       ("cone-256r-32v-hc", 97)])
+def test_coded_rows_rebuild_the_walk(hw, name, step):
+    # coded rows (a column's in-plane path shared by its rays, plus per ray
+    # piece / slice bits) rebuilt without the stored row equal the walk's row
+    # bit for bit; every ray of the configured scans codes (none explicit)
+    w = cases()[name] if name in cases() else synth.get(name)
+    o = Oracle(w)
+    wk = Walk(hw, w, o)
+    m = hw.hw_columns()
+    assert m > 0 and hw.hw_column_gaps() == 0
+    ids = np.zeros(wk.cap, dtype=np.uint32)
+    lens = np.zeros(wk.cap, dtype=np.float32)
+    info = np.zeros(4, dtype=np.int64)
+    coded = 0
+    for r in range(0, o.n_rays, step):
+        n = hw.hw_code_ray(r, ids.ctypes.data, lens.ctypes.data, wk.cap, info.ctypes.data)
+        assert n >= 0, (r, n)          # -1: rebuilt row differs, -2: left explicit
+        if n:
+            coded += 1
+            c2, l2 = wk.row(r)
+            assert np.array_equal(ids[:n].astype(np.int64), c2)
+            assert np.array_equal(lens[:n], l2.astype(np.float32))
+    assert coded > 0
