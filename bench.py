@@ -125,10 +125,14 @@ def host_info() -> dict:
     return {"nproc": os.cpu_count(), "model": model}
 
 
-def cpu_baseline(w, lattice, P, rows):
+def cpu_baseline(w, lattice, P, rows, sweeps_1: int = 2):
     """The FP64 oracle on a bounded sample of the same workload: the rays of
-    `rows` central detector rows, traced, then MART over all views and sweeps
-    with every other row empty."""
+    `rows` central detector rows (every other row empty), traced once, then
+    the MART sweep loop over all views timed on its own, with every host
+    thread the oracle may use (all of the workload's sweeps) and with one
+    thread (`sweeps_1` sweeps; the rate is per update either way).  The two
+    runs give the same image bit for bit (the rays of a colour class share no
+    cell)."""
     from oracle import Oracle
     from oracle.oracle import CSR
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -149,14 +153,21 @@ def cpu_baseline(w, lattice, P, rows):
     order = np.argsort(rays)
     csr = CSR(rowptr, np.concatenate([cells[i] for i in order]), np.concatenate([lens[i] for i in order]))
     t1 = time.perf_counter()
-    o.mart(csr, lattice, P, np.ones(o.n_cells), w.sweeps, w.beta)
+    o.mart(csr, lattice, P, np.ones(o.n_cells), w.sweeps, w.beta, nthreads=threads)
     t2 = time.perf_counter()
-    updates = w.n_views * csr.nnz * w.sweeps
-    return {"value": updates / (t2 - t0), "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "host": host_info(),
+    o.mart(csr, lattice, P, np.ones(o.n_cells), sweeps_1, w.beta, nthreads=1)
+    t3 = time.perf_counter()
+    per_sweep = w.n_views * csr.nnz
+    rate_n = per_sweep * w.sweeps / (t2 - t1)
+    rate_1 = per_sweep * sweeps_1 / (t3 - t2)
+    return {"value": rate_n, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "threads_n": {"threads": threads, "updates_per_s": rate_n, "sweeps": w.sweeps, "s": t2 - t1},
+            "threads_1": {"threads": 1, "updates_per_s": rate_1, "sweeps": sweeps_1, "s": t3 - t2},
+            "trace_s": t1 - t0, "host": host_info(),
             "sample": f"{rows} central detector rows ({len(rays)} rays, {csr.nnz} reference nonzeros) of "
-                      f"{w.name}: trace {t1 - t0:.2f} s + {w.sweeps} MART sweeps over {w.n_views} views "
-                      f"{t2 - t1:.2f} s, FP64"}
+                      f"{w.name}, FP64; MART sweep loop over {w.n_views} views timed alone: {w.sweeps} sweeps on "
+                      f"{threads} threads {t2 - t1:.2f} s, {sweeps_1} sweeps on 1 thread {t3 - t2:.2f} s; "
+                      f"trace (serial, not in the rate) {t1 - t0:.2f} s"}
 
 
 def bench_batch2d(args):

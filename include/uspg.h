@@ -169,15 +169,37 @@ typedef struct {
 
 /* Traces every view-0 ray through the grid on the device (FP64 geometry),
  * stores the reference rows (one entry per traversed cell, duplicates merged)
- * and colours the rays into cell-disjoint lattice classes.  Allocates the
- * handle's device memory with hipMalloc; synchronises `stream` once (to size
- * the rows).  The grid must outlive the coefficients. */
-int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *scan, void *stream,
-                      uspg_coeffs **out);
+ * and colours the rays into cell-disjoint lattice classes, in two calls:
+ *  1. Size query: dev_ws == NULL.  Validates the arguments, runs the count
+ *     pass and sets *ws_needed to the bytes of device memory the handle will
+ *     hold; *out receives a pending handle (it keeps the counts; every call
+ *     except a fill call, uspg_coeffs_info and uspg_free_coeffs refuses it
+ *     with USPG_E_ARG).  *out is read on entry: it must be NULL or a
+ *     pending handle (then it is returned as is).
+ *  2. Fill: dev_ws != NULL, ws_bytes >= the size, *out = the pending handle
+ *     of this grid and an equal scan description (or NULL: the counts then
+ *     run in this call).  Every device array of the handle is carved out of
+ *     dev_ws (256-byte aligned pieces); *out receives the built handle.
+ *     ws_needed (nullable) receives the size.  A short work space returns
+ *     USPG_E_NOMEM with nothing written to it (a pending handle passed in
+ *     stays pending); any other failure frees the handle and sets *out to
+ *     NULL.
+ * dev_ws is device memory owned by the caller (e.g. a torch tensor, so that
+ * the coefficients count in the caller's memory accounting); the handle must
+ * not outlive it and uspg_free_coeffs does not free it.  The library's own
+ * temporary device memory during the calls is freed before they return.
+ * With SEGMENTS the records and kept view rows depend on the whole colouring,
+ * so the size query builds them in library memory and the fill moves them
+ * into dev_ws.  The grid must outlive the coefficients.  Synchronises
+ * `stream` (several times). */
+int uspg_build_coeffs(const uspg_grid *g, const uspg_scan_desc *scan, void *dev_ws, size_t ws_bytes,
+                      size_t *ws_needed, void *stream, uspg_coeffs **out);
 
 /* Sizes of the reference rows and the chosen lattice (classes are
  * c = (w mod colour_v) * colour_u + (u mod colour_u)).  With SEGMENTS,
- * nnz_ref and max_row count segment records.  NULL skips. */
+ * nnz_ref and max_row count segment records.  device_bytes is the work
+ * space the handle occupies.  On a pending handle the lattice is not
+ * chosen yet (0).  NULL skips. */
 int uspg_coeffs_info(const uspg_coeffs *c, int64_t *nnz_ref, int64_t *n_rays,
                      int32_t *colour_u, int32_t *colour_v, int32_t *max_row,
                      int64_t *device_bytes);
@@ -257,15 +279,17 @@ int mart_run(const uspg_coeffs *c, int32_t dtype, const void *proj, void *image,
 int mart_run_noalloc(const uspg_coeffs *c, int32_t dtype, const void *proj, void *image,
                      int32_t n_sweeps, double beta, double tol, int32_t *sweeps_done, void *stream);
 
-/* Timing of mart_run's batch kernels (profiling aid).  enable = 1 resets the
- * accumulators and turns timing on: every later mart_run records one HIP
- * event pair on its stream around its sequence of (view, class) batch
- * kernels (nothing between them), synchronises the stream at its end and
- * adds the elapsed time and the number of batch launches (calls on a stream
- * under graph capture are not timed).  enable = 0 turns
- * timing off.  batch_ms and batch_launches (host, nullable) receive the
- * totals so far.  Process-wide; not meant for concurrent mart_run calls. */
-int uspg_mart_timing(int32_t enable, double *batch_ms, int64_t *batch_launches);
+/* Timing of mart_run's batch kernels on one stream (profiling aid), kept
+ * per stream so that calls on other streams neither add to it nor disturb
+ * it.  enable = 1 resets `stream`'s accumulators and turns its timing on:
+ * every later mart_run on that stream records one HIP event pair around its
+ * sequence of (view, class) batch kernels (nothing between them),
+ * synchronises the stream at its end and adds the elapsed time and the
+ * number of batch launches (calls under graph capture and
+ * mart_run_noalloc calls are not timed).  enable = 0 turns the stream's
+ * timing off and forgets it.  batch_ms and batch_launches (host, nullable)
+ * receive the stream's totals so far.  Thread-safe. */
+int uspg_mart_timing(int32_t enable, void *stream, double *batch_ms, int64_t *batch_launches);
 
 /* ---- USPG -> Cartesian grid (Sec. II.B) -----------------------------------
  * cart: device [n_slices][nc][nc]; pixel (ix, iy) covers the square of side
@@ -425,6 +449,15 @@ int mart_run_slabs(const uspg_slabs *s, int32_t dtype, const void *proj, void *i
                    size_t work_bytes, int32_t n_sweeps, double beta, void *stream);
 
 void uspg_free_slabs(uspg_slabs *s);
+
+/* ---- allocation accounting (tests of error paths) --------------------------
+ * *live (nullable) receives the number of device allocations the library
+ * holds right now (handles' own memory and temporaries; not caller work
+ * space).  fail_after > 0 makes the fail_after-th library device allocation
+ * from now fail as if the device were out of memory (the call then returns
+ * USPG_E_NOMEM); 0 cancels a pending one; < 0 leaves it as it is.
+ * Process-wide; meant for tests. */
+int uspg_debug_alloc(int32_t fail_after, int64_t *live);
 
 /* ---- debug checks -----------------------------------------------------------
  * Race check of the MART order (Sec. III.D: a class batch equals its rays

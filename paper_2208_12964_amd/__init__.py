@@ -63,7 +63,8 @@ def lib():
     L.uspg_grid_tables.argtypes = [P, P, P]
     L.uspg_free_grid.argtypes = [P]
     L.uspg_free_grid.restype = None
-    L.uspg_build_coeffs.argtypes = [P, C.POINTER(_ScanDesc), P, C.POINTER(P)]
+    L.uspg_build_coeffs.argtypes = [P, C.POINTER(_ScanDesc), P, SZ, P, P, C.POINTER(P)]
+    L.uspg_debug_alloc.argtypes = [I32, P]
     L.uspg_coeffs_info.argtypes = [P, P, P, P, P, P, P]
     L.uspg_coeffs_row.argtypes = [P, I32, I64, P, P, I32, P]
     L.uspg_coeffs_conflicts.argtypes = [P, P]
@@ -76,7 +77,7 @@ def lib():
     L.mart_run.argtypes = [P, I32, P, P, P, SZ, I32, D, D, P, P]
     L.mart_run_noalloc.argtypes = [P, I32, P, P, I32, D, D, P, P]
     L.uspg_to_cartesian.argtypes = [P, I32, P, P, I32, I32, P]
-    L.uspg_mart_timing.argtypes = [I32, P, P]
+    L.uspg_mart_timing.argtypes = [I32, P, P, P]
     L.uspg_build_batch.argtypes = [I32, P, I32, C.POINTER(P)]
     L.uspg_batch_set.argtypes = [P, I32, I32, I32]
     L.uspg_batch_info.argtypes = [P, P, P, P, P, P]
@@ -105,7 +106,8 @@ def lib():
                  "uspg_to_cartesian", "uspg_mart_timing", "uspg_build_batch", "uspg_batch_set",
                  "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_engine_create",
                  "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info", "uspg_build_slabs",
-                 "uspg_slabs_info", "mart_run_slabs", "uspg_check_lattice", "uspg_check_projections"):
+                 "uspg_slabs_info", "mart_run_slabs", "uspg_check_lattice", "uspg_check_projections",
+                 "uspg_debug_alloc"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -180,9 +182,17 @@ class Coeffs:
         d = _ScanDesc(GEOMETRY[geometry], n_views, span, det_u, det_v, det_half_u, det_half_v,
                       src_axis, src_det, WEIGHTS[weights], DTYPE[coeff_dtype], colour[0], colour[1],
                       1 if quarter else 0, {"keep": 0, "rebin": 1}[view_rows], {"coded": 0, "stored": 1}[rows])
+        # two calls: the size query leaves a pending handle with the counts,
+        # the fill carves the coefficients out of a torch work space
         h = C.c_void_p()
-        _check(L.uspg_build_coeffs(grid.handle, C.byref(d), C.c_void_p(_stream(stream)), C.byref(h)))
+        need = C.c_size_t()
+        st = C.c_void_p(_stream(stream))
+        _check(L.uspg_build_coeffs(grid.handle, C.byref(d), None, 0, C.byref(need), st, C.byref(h)))
         self.handle = h
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=dev)
+        _check(L.uspg_build_coeffs(grid.handle, C.byref(d), C.c_void_p(self.workspace.data_ptr()),
+                                   self.workspace.numel(), C.byref(need), st, C.byref(h)))
         self.n_views, self.det_u, self.det_v = n_views, det_u, det_v
         nnz, nr, ku, kv, mr, db = (C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(),
                                    C.c_int64())
@@ -348,12 +358,21 @@ def to_cartesian(grid: Grid, image: torch.Tensor, nc: int, mode: str = "point",
     return out
 
 
-def mart_timing(enable: bool):
-    """Turn batch-kernel timing of mart_run on (resets) or off; returns
-    (batch_ms, batch_launches) accumulated so far."""
+def mart_timing(enable: bool, stream=None):
+    """Turn batch-kernel timing of mart_run on `stream` (None: the current
+    stream) on (resets) or off; returns (batch_ms, batch_launches) of that
+    stream so far."""
     ms, n = C.c_double(), C.c_int64()
-    _check(lib().uspg_mart_timing(1 if enable else 0, C.byref(ms), C.byref(n)))
+    _check(lib().uspg_mart_timing(1 if enable else 0, C.c_void_p(_stream(stream)), C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def debug_alloc(fail_after: int = -1) -> int:
+    """``uspg_debug_alloc``: live library device allocations; fail_after > 0
+    makes that library allocation from now fail (0 cancels)."""
+    live = C.c_int64()
+    _check(lib().uspg_debug_alloc(int(fail_after), C.byref(live)))
+    return live.value
 
 
 def _ptr_array(ptrs):
@@ -546,7 +565,8 @@ EXPORTED = ("uspg_build_grid", "uspg_grid_info", "uspg_grid_tables", "uspg_free_
             "uspg_batch_info", "mart_run_batch", "uspg_batch_autotune", "uspg_free_batch",
             "uspg_engine_create", "uspg_engine_admit", "uspg_engine_step", "uspg_engine_info",
             "uspg_engine_destroy", "uspg_build_slabs", "uspg_slabs_info", "uspg_slabs_workspace_bytes",
-            "mart_run_slabs", "uspg_free_slabs", "uspg_check_lattice", "uspg_check_projections")
+            "mart_run_slabs", "uspg_free_slabs", "uspg_check_lattice", "uspg_check_projections",
+            "uspg_debug_alloc")
 
 
 def reconstruct(w, proj: torch.Tensor, dtype=torch.float32, coeff_dtype=None, colour=(0, 0),

@@ -571,6 +571,7 @@ int uspg_build_batch(int32_t n, const uspg_coeffs *const *coeffs, int32_t dtype,
     USPG_HIP(hipGetDevice(&dev));
     for (int i = 0; i < n; ++i) {
         if (!coeffs[i]) return fail(USPG_E_ARG, "null coefficients in batch");
+        if (coeffs[i]->pending) return fail(USPG_E_ARG, "pending coefficients in batch");
         if (coeffs[i]->device != dev) return fail(USPG_E_ARG, "coefficients on another device");
         if (coeffs[i]->segments && !kept_rows(coeffs[i]))
             return fail(USPG_E_ARG, "segment-record coefficients join a batch only with their view rows kept");
@@ -737,6 +738,7 @@ int uspg_engine_admit(uspg_engine *e, const uspg_coeffs *c, const void *proj, vo
 {
     if (!e || !c || !proj || !image || !work) return fail(USPG_E_ARG, "null argument");
     if (n_sweeps <= 0 || !(beta > 0)) return fail(USPG_E_ARG, "n_sweeps > 0 and beta > 0");
+    if (c->pending) return fail(USPG_E_ARG, "pending coefficients");
     if (c->segments && !kept_rows(c))
         return fail(USPG_E_ARG, "segment-record coefficients join an engine only with their view rows kept");
     if (stored_coeff_dtype(c) != e->coeff_dtype) return fail(USPG_E_ARG, "coefficient type differs from the engine's");

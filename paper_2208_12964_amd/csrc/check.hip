@@ -79,7 +79,7 @@ int uspg_check_lattice(const uspg_coeffs *c, int32_t view, int32_t ku, int32_t k
     if (view < 0 || view >= c->scan.n_views) return fail(USPG_E_ARG, "view out of range");
     const int U = c->scan.det_u, V = c->scan.det_v;
     if (ku < 1 || kv < 1 || ku > U || kv > V) return fail(USPG_E_ARG, "lattice out of range");
-    int rc = check_device(c->device);
+    int rc = check_coeffs(c);
     if (rc != USPG_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     DevBuf hits, extra;
@@ -135,7 +135,7 @@ int uspg_check_projections(const uspg_coeffs *c, int32_t dtype, const void *proj
 {
     if (!c || !proj || !n_bad) return fail(USPG_E_ARG, "null argument");
     if (dtype != USPG_F32 && dtype != USPG_F64) return fail(USPG_E_ARG, "dtype");
-    int rc = check_device(c->device);
+    int rc = check_coeffs(c);
     if (rc != USPG_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = (int64_t)c->scan.n_views * c->nrays;

@@ -3,7 +3,7 @@
 // the stored row entry by entry.
 //
 //   col_count / col_fill   one thread walks one column's in-plane line
-//   ray_nwords             mask words of each ray from its row length (scanned)
+//   ray_nwords             mask words of each ray from its entry count (scanned)
 //   ray_code               one thread codes one ray and writes its bits, or
 //                          leaves it explicit
 #include <cmath>
@@ -52,14 +52,13 @@ struct StoredRow {
     }
 };
 
-// Mask words of every ray (two per chunk of 64 entries), from its stored
-// row length; explicit rays keep their (unused) slots.
-__global__ __launch_bounds__(256) void ray_nwords(int64_t nrays, const int64_t *rowptr, uint32_t *nwords)
+// Mask words of every ray (two per chunk of 64 entries), from its row
+// length; explicit rays keep their (unused) slots.
+__global__ __launch_bounds__(256) void ray_nwords(int64_t nrays, const uint32_t *cnt, uint32_t *nwords)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrays) return;
-    const int64_t n = rowptr[r + 1] - rowptr[r];
-    nwords[r] = (uint32_t)(2 * ((n + 63) / 64));
+    nwords[r] = 2 * ((cnt[r] + 63) / 64);
 }
 
 // Code of every ray, checked against its stored row; a ray whose row is not
@@ -90,8 +89,30 @@ __global__ __launch_bounds__(256) void ray_code(walk::TraceGeo G, CodeGeo Q, int
     if (n > 0) atomicAdd(counts + (ok ? 0 : 1), 1ull);
 }
 
+// Column records per column (scanned into colptr) and mask-word offsets per
+// ray (scanned into woff) from the entry counts of the count pass.
+int code_offsets(uspg_coeffs *c, int64_t *colptr, int64_t *woff, hipStream_t s)
+{
+    const walk::TraceGeo G = trace_geo(c);
+    if (!G.kq || !G.hq || !c->pend_cnt.p || !colptr || !woff)
+        return fail(USPG_E_INTERNAL, "coded rows: tables or counts not on the device");
+    const int U = c->scan.det_u;
+    const int64_t nrays = c->nrays;
+    int rc;
+    DevBuf cnt, nwords;
+    if ((rc = cnt.alloc(sizeof(uint32_t) * (U + 1))) != USPG_OK) return rc;
+    if ((rc = nwords.alloc(sizeof(uint32_t) * (nrays + 1))) != USPG_OK) return rc;
+    hipLaunchKernelGGL(col_count, dim3((U + 255) / 256), dim3(256), 0, s, G, cnt.as<uint32_t>());
+    if ((rc = exclusive_scan_u32_to_i64(cnt.as<uint32_t>(), colptr, U, s)) != USPG_OK) return rc;
+    hipLaunchKernelGGL(ray_nwords, dim3((unsigned)((nrays + 255) / 256)), dim3(256), 0, s, nrays,
+                       c->pend_cnt.as<uint32_t>(), nwords.as<uint32_t>());
+    if ((rc = exclusive_scan_u32_to_i64(nwords.as<uint32_t>(), woff, nrays, s)) != USPG_OK) return rc;
+    USPG_HIP(hipGetLastError());
+    return USPG_OK;
+}
+
 template <class TC>
-int build_typed(uspg_coeffs *c, hipStream_t s)
+int fill_typed(uspg_coeffs *c, hipStream_t s)
 {
     const walk::TraceGeo G = trace_geo(c);
     const uspg_grid *g = c->g;
@@ -99,64 +120,53 @@ int build_typed(uspg_coeffs *c, hipStream_t s)
     const int U = c->scan.det_u;
     const int64_t nrays = c->nrays;
     const int binary = c->scan.weights == USPG_WEIGHTS_BINARY;
-    int rc = USPG_OK;
-    DevBuf cnt, nwords, woff, counts;
-    do {
-        // column paths
-        if ((rc = cnt.alloc(sizeof(uint32_t) * (U + 1))) != USPG_OK) break;
-        if ((rc = c->d_colptr.alloc(sizeof(int64_t) * (U + 1))) != USPG_OK) break;
-        hipLaunchKernelGGL(col_count, dim3((U + 255) / 256), dim3(256), 0, s, G, cnt.as<uint32_t>());
-        if ((rc = exclusive_scan_u32_to_i64(cnt.as<uint32_t>(), c->d_colptr.as<int64_t>(), U, s)) != USPG_OK) break;
-        int64_t nrec = 0;
-        USPG_HIP(hipMemcpy(&nrec, c->d_colptr.as<int64_t>() + U, sizeof(int64_t), hipMemcpyDeviceToHost));
-        if (nrec >= ((int64_t)1 << 31)) { rc = fail(USPG_E_ARG, "coded rows: more than 2^31 column records"); break; }
-        if ((rc = c->d_colt.alloc(sizeof(double) * nrec)) != USPG_OK) break;
-        if ((rc = c->d_colid.alloc(sizeof(uint32_t) * nrec)) != USPG_OK) break;
-        hipLaunchKernelGGL(col_fill, dim3((U + 255) / 256), dim3(256), 0, s, G, c->d_colptr.as<int64_t>(),
-                           c->d_colt.as<double>(), c->d_colid.as<uint32_t>());
-        USPG_HIP(hipGetLastError());
-        // mask words at the offsets of the row lengths, then the codes
-        if ((rc = nwords.alloc(sizeof(uint32_t) * (nrays + 1))) != USPG_OK) break;
-        if ((rc = woff.alloc(sizeof(int64_t) * (nrays + 1))) != USPG_OK) break;
-        const unsigned rb = (unsigned)((nrays + 255) / 256);
-        hipLaunchKernelGGL(ray_nwords, dim3(rb), dim3(256), 0, s, nrays, c->rowptr.as<int64_t>(), nwords.as<uint32_t>());
-        if ((rc = exclusive_scan_u32_to_i64(nwords.as<uint32_t>(), woff.as<int64_t>(), nrays, s)) != USPG_OK) break;
-        int64_t nw = 0;
-        USPG_HIP(hipMemcpy(&nw, woff.as<int64_t>() + nrays, sizeof(int64_t), hipMemcpyDeviceToHost));
-        if (nw >= ((int64_t)1 << 31)) { rc = fail(USPG_E_ARG, "coded rows: more than 2^31 mask words"); break; }
-        if ((rc = c->d_words.alloc(sizeof(uint64_t) * (nw > 0 ? nw : 1))) != USPG_OK) break;
-        if ((rc = c->d_codes.alloc(sizeof(RayCode) * nrays)) != USPG_OK) break;
-        if ((rc = counts.alloc(2 * sizeof(unsigned long long))) != USPG_OK) break;
-        USPG_HIP(hipMemsetAsync(counts.p, 0, 2 * sizeof(unsigned long long), s));
-        hipLaunchKernelGGL(ray_code<TC>, dim3(rb), dim3(256), 0, s, G, Q, nrays, c->rowptr.as<int64_t>(),
-                           c->coef.as<Coef<TC>>(), c->d_colptr.as<int64_t>(), c->d_colt.as<double>(),
-                           c->d_colid.as<uint32_t>(), binary, woff.as<int64_t>(), c->d_codes.as<RayCode>(),
-                           c->d_words.as<uint64_t>(), counts.as<unsigned long long>());
-        USPG_HIP(hipGetLastError());
-        unsigned long long hc[2] = {0, 0};
-        USPG_HIP(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
-        USPG_HIP(hipStreamSynchronize(s));
-        c->coded_rays = (int64_t)hc[0];
-        c->explicit_rays = (int64_t)hc[1];
-        c->coded = true;
-    } while (0);
-    if (rc != USPG_OK) {
-        c->d_colptr.release();
-        c->d_colt.release();
-        c->d_colid.release();
-        c->d_codes.release();
-        c->d_words.release();
-        c->coded = false;
-    }
-    return rc;
+    int rc;
+    if (!c->rowptr.p || !c->coef.p || !c->d_colptr.p || !c->d_colt.p || !c->d_colid.p || !c->d_codes.p ||
+        !c->d_words.p)
+        return fail(USPG_E_INTERNAL, "coded rows: rows or code buffers not on the device");
+    DevBuf woff, counts;
+    if ((rc = woff.alloc(sizeof(int64_t) * (nrays + 1))) != USPG_OK) return rc;
+    if ((rc = counts.alloc(2 * sizeof(unsigned long long))) != USPG_OK) return rc;
+    if ((rc = code_offsets(c, c->d_colptr.as<int64_t>(), woff.as<int64_t>(), s)) != USPG_OK) return rc;
+    hipLaunchKernelGGL(col_fill, dim3((U + 255) / 256), dim3(256), 0, s, G, c->d_colptr.as<int64_t>(),
+                       c->d_colt.as<double>(), c->d_colid.as<uint32_t>());
+    USPG_HIP(hipMemsetAsync(counts.p, 0, 2 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(ray_code<TC>, dim3((unsigned)((nrays + 255) / 256)), dim3(256), 0, s, G, Q, nrays,
+                       c->rowptr.as<int64_t>(), c->coef.as<Coef<TC>>(), c->d_colptr.as<int64_t>(),
+                       c->d_colt.as<double>(), c->d_colid.as<uint32_t>(), binary, woff.as<int64_t>(),
+                       c->d_codes.as<RayCode>(), c->d_words.as<uint64_t>(), counts.as<unsigned long long>());
+    USPG_HIP(hipGetLastError());
+    unsigned long long hc[2] = {0, 0};
+    USPG_HIP(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+    USPG_HIP(hipStreamSynchronize(s));
+    c->coded_rays = (int64_t)hc[0];
+    c->explicit_rays = (int64_t)hc[1];
+    c->coded = true;
+    return USPG_OK;
 }
 
 }  // namespace
 
-int build_row_codes(uspg_coeffs *c, hipStream_t s)
+int code_count(uspg_coeffs *c, hipStream_t s)
 {
-    if (c->scan.coeff_dtype == USPG_F64) return build_typed<double>(c, s);
-    return build_typed<float>(c, s);
+    const int U = c->scan.det_u;
+    const int64_t nrays = c->nrays;
+    int rc;
+    DevBuf colptr, woff;
+    if ((rc = colptr.alloc(sizeof(int64_t) * (U + 1))) != USPG_OK) return rc;
+    if ((rc = woff.alloc(sizeof(int64_t) * (nrays + 1))) != USPG_OK) return rc;
+    if ((rc = code_offsets(c, colptr.as<int64_t>(), woff.as<int64_t>(), s)) != USPG_OK) return rc;
+    USPG_HIP(hipMemcpy(&c->pend_nrec, colptr.as<int64_t>() + U, sizeof(int64_t), hipMemcpyDeviceToHost));
+    USPG_HIP(hipMemcpy(&c->pend_nwords, woff.as<int64_t>() + nrays, sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (c->pend_nrec >= ((int64_t)1 << 31) || c->pend_nwords >= ((int64_t)1 << 31))
+        return fail(USPG_E_ARG, "coded rows: more than 2^31 column records or mask words");
+    return USPG_OK;
+}
+
+int code_fill(uspg_coeffs *c, hipStream_t s)
+{
+    if (c->scan.coeff_dtype == USPG_F64) return fill_typed<double>(c, s);
+    return fill_typed<float>(c, s);
 }
 
 }  // namespace uspg

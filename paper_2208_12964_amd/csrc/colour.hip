@@ -73,9 +73,9 @@ int conflict_marks(const int64_t *rowptr, const uint32_t *ids, int stride, int64
     uint32_t *cnt = nullptr, *cptr = nullptr, *rays = nullptr;
     int rc = USPG_OK;
     do {
-        if (hipMalloc((void **)&cnt, sizeof(uint32_t) * (ncells + 1)) != hipSuccess ||
-            hipMalloc((void **)&cptr, sizeof(uint32_t) * (ncells + 1)) != hipSuccess ||
-            hipMalloc((void **)&rays, sizeof(uint32_t) * (nnz > 0 ? nnz : 1)) != hipSuccess) {
+        if (dev_malloc((void **)&cnt, sizeof(uint32_t) * (ncells + 1)) != hipSuccess ||
+            dev_malloc((void **)&cptr, sizeof(uint32_t) * (ncells + 1)) != hipSuccess ||
+            dev_malloc((void **)&rays, sizeof(uint32_t) * (nnz > 0 ? nnz : 1)) != hipSuccess) {
             rc = fail(USPG_E_NOMEM, "colouring: device allocation failed");
             break;
         }
@@ -96,7 +96,7 @@ int conflict_marks(const int64_t *rowptr, const uint32_t *ids, int stride, int64
         if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "colouring: launch failed"); break; }
         if (hipStreamSynchronize(s) != hipSuccess) { rc = fail(USPG_E_HIP, "colouring failed"); break; }
     } while (0);
-    (void)hipFree(cnt); (void)hipFree(cptr); (void)hipFree(rays);
+    (void)dev_free(cnt); (void)dev_free(cptr); (void)dev_free(rays);
     return rc;
 }
 
@@ -132,7 +132,7 @@ int colour_reference_view(uspg_coeffs *c, hipStream_t s)
     const int U = c->scan.det_u, V = c->scan.det_v;
     uint8_t *mark = nullptr;
     c->mark.assign((size_t)U * V, 0);
-    if (hipMalloc((void **)&mark, (size_t)U * V) != hipSuccess) return fail(USPG_E_NOMEM, "colouring: allocation");
+    if (dev_malloc((void **)&mark, (size_t)U * V) != hipSuccess) return fail(USPG_E_NOMEM, "colouring: allocation");
     int rc = USPG_OK;
     if (hipMemsetAsync(mark, 0, (size_t)U * V, s) != hipSuccess) rc = fail(USPG_E_HIP, "colouring: memset failed");
     // ids live in the device layout, as the first word of each (id,
@@ -143,7 +143,7 @@ int colour_reference_view(uspg_coeffs *c, hipStream_t s)
                             mark, s);
     if (rc == USPG_OK && hipMemcpy(c->mark.data(), mark, (size_t)U * V, hipMemcpyDeviceToHost) != hipSuccess)
         rc = fail(USPG_E_HIP, "colouring: copy failed");
-    (void)hipFree(mark);
+    (void)dev_free(mark);
     if (rc != USPG_OK) return rc;
     return choose_lattice(c);
 }

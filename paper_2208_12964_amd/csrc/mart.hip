@@ -16,6 +16,8 @@
 // scatter; longer rows are re-read in a second pass.
 #include <algorithm>
 #include <atomic>
+#include <mutex>
+#include <unordered_map>
 
 #include "mart_batch.hpp"
 #include "mart_coded.hpp"
@@ -223,10 +225,6 @@ BatchArgs<T, TC> batch_args(const uspg_coeffs *c, const T *proj, T *f, double be
     return A;
 }
 
-// Batch-kernel timing (uspg_mart_timing).
-std::atomic<int> g_timing{0};
-std::atomic<int64_t> g_timing_launches{0};
-std::atomic<int64_t> g_timing_ns{0};
 
 template <class T, class TC>
 int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_sweeps, double beta,
@@ -290,8 +288,7 @@ int run_typed(const uspg_coeffs *c, const T *proj, T *image, void *work, int n_s
         USPG_HIP(hipEventSynchronize(ev1));
         float ms = 0.f;
         USPG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-        g_timing_ns += (int64_t)((double)ms * 1e6);
-        g_timing_launches += launches;
+        mart_timing_add(s, (int64_t)((double)ms * 1e6), launches);
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);
     }
@@ -353,23 +350,47 @@ UntimedScope::~UntimedScope() { t_untimed = prev; }
 
 // Timing records and waits on events, which a stream under graph capture
 // cannot do: captured calls are not timed.
-bool mart_timing_on(hipStream_t s) { return g_timing.load() != 0 && !t_untimed && !stream_capturing(s); }
+// Batch-kernel timing (uspg_mart_timing), kept per stream.
+namespace {
+struct TimingAcc {
+    bool on = false;
+    int64_t ns = 0, launches = 0;
+};
+std::mutex g_timing_mu;
+std::unordered_map<hipStream_t, TimingAcc> g_timing;
+}  // namespace
 
-void mart_timing_add(int64_t ns, int64_t launches)
+bool mart_timing_on(hipStream_t s)
 {
-    g_timing_ns += ns;
-    g_timing_launches += launches;
+    if (t_untimed) return false;
+    {
+        std::lock_guard<std::mutex> lk(g_timing_mu);
+        auto it = g_timing.find(s);
+        if (it == g_timing.end() || !it->second.on) return false;
+    }
+    return !stream_capturing(s);
 }
 
-int mart_timing(int enable, double *batch_ms, int64_t *batch_launches)
+void mart_timing_add(hipStream_t s, int64_t ns, int64_t launches)
 {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    TimingAcc &a = g_timing[s];
+    a.ns += ns;
+    a.launches += launches;
+}
+
+int mart_timing(int enable, hipStream_t s, double *batch_ms, int64_t *batch_launches)
+{
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    TimingAcc &a = g_timing[s];
     if (enable) {
-        g_timing_ns = 0;
-        g_timing_launches = 0;
+        a.ns = 0;
+        a.launches = 0;
     }
-    g_timing = enable ? 1 : 0;
-    if (batch_ms) *batch_ms = (double)g_timing_ns.load() * 1e-6;
-    if (batch_launches) *batch_launches = g_timing_launches.load();
+    a.on = enable != 0;
+    if (batch_ms) *batch_ms = (double)a.ns * 1e-6;
+    if (batch_launches) *batch_launches = a.launches;
+    if (!enable) g_timing.erase(s);
     return USPG_OK;
 }
 

@@ -292,7 +292,7 @@ int run_segments(const uspg_coeffs *c, const T *proj, T *image, void *work, int 
         USPG_HIP(hipEventSynchronize(ev1));
         float ms = 0.f;
         USPG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-        mart_timing_add((int64_t)((double)ms * 1e6), launches);
+        mart_timing_add(s, (int64_t)((double)ms * 1e6), launches);
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);
     }

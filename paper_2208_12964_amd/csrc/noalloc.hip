@@ -61,7 +61,7 @@ extern "C" int mart_run_noalloc(const uspg_coeffs *c, int32_t dtype, const void 
         return fail(USPG_E_NOMEM, "mart_run_noalloc: the problem needs " + std::to_string(need) +
                                       " bytes of work space, more than the fixed " +
                                       std::to_string((size_t)USPG_NOALLOC_SCRATCH_BYTES));
-    int rc = check_device(c->device);
+    int rc = check_coeffs(c);
     if (rc != USPG_OK) return rc;
     if (tol > 0 && stream_capturing((hipStream_t)stream))
         return fail(USPG_E_ARG, "tol > 0 synchronises the stream once per sweep and cannot be graph-captured");

@@ -89,13 +89,13 @@ int scan_impl(const uint32_t *in, T *out, int64_t n, hipStream_t s)
         return USPG_OK;
     }
     T *tot = nullptr;
-    USPG_HIP(hipMalloc((void **)&tot, sizeof(T) * ntiles));
+    if (dev_malloc((void **)&tot, sizeof(T) * ntiles) != hipSuccess) return fail(USPG_E_NOMEM, "device allocation failed");
     hipLaunchKernelGGL(tile_totals<T>, dim3((unsigned)ntiles), dim3(kThreads), 0, s, in, n, tot);
     hipLaunchKernelGGL(scan_totals<T>, dim3(1), dim3(kThreads), 0, s, tot, ntiles, out + n);
     hipLaunchKernelGGL(tile_scan<T>, dim3((unsigned)ntiles), dim3(kThreads), 0, s, in, n, tot, out);
     USPG_HIP(hipGetLastError());
     USPG_HIP(hipStreamSynchronize(s));
-    USPG_HIP(hipFree(tot));
+    USPG_HIP(dev_free(tot));
     return USPG_OK;
 }
 

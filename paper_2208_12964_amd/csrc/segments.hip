@@ -219,9 +219,9 @@ int segments_reference_view(uspg_coeffs *c, hipStream_t s)
     const unsigned blocks = (unsigned)((nrays + 255) / 256);
     uint32_t *cnt = nullptr;
     unsigned int *mx = nullptr;
-    USPG_HIP(hipMalloc((void **)&cnt, sizeof(uint32_t) * (nrays + 1)));
-    if (hipMalloc((void **)&mx, sizeof(unsigned int)) != hipSuccess) {
-        (void)hipFree(cnt);
+    if (dev_malloc((void **)&cnt, sizeof(uint32_t) * (nrays + 1)) != hipSuccess) return fail(USPG_E_NOMEM, "device allocation failed");
+    if (dev_malloc((void **)&mx, sizeof(unsigned int)) != hipSuccess) {
+        (void)dev_free(cnt);
         return fail(USPG_E_NOMEM, "segments: allocation failed");
     }
     int rc = USPG_OK;
@@ -264,8 +264,8 @@ int segments_reference_view(uspg_coeffs *c, hipStream_t s)
         if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "seg_fill launch failed"); break; }
         if (hipStreamSynchronize(s) != hipSuccess) { rc = fail(USPG_E_HIP, "seg_fill failed"); break; }
     } while (0);
-    (void)hipFree(cnt);
-    (void)hipFree(mx);
+    (void)dev_free(cnt);
+    (void)dev_free(mx);
     return rc;
 }
 
@@ -294,8 +294,8 @@ int colour_segments(uspg_coeffs *c, hipStream_t s)
     uint8_t *mark = nullptr;
     int rc = USPG_OK;
     do {
-        if (hipMalloc((void **)&cnt, sizeof(uint32_t) * (nrays + 1)) != hipSuccess ||
-            hipMalloc((void **)&mark, (size_t)U * V) != hipSuccess) {
+        if (dev_malloc((void **)&cnt, sizeof(uint32_t) * (nrays + 1)) != hipSuccess ||
+            dev_malloc((void **)&mark, (size_t)U * V) != hipSuccess) {
             rc = fail(USPG_E_NOMEM, "segment colouring: allocation failed");
             break;
         }
@@ -328,7 +328,7 @@ int colour_segments(uspg_coeffs *c, hipStream_t s)
         if (keep && (rc = c->view_coef.alloc(sizeof(Coef<float>) * (size_t)std::max<int64_t>(total, 1))) != USPG_OK)
             break;
         c->view_max_row = (int32_t)longest;
-        if (hipMalloc((void **)&ids, sizeof(uint32_t) * (size_t)widest) != hipSuccess) {
+        if (dev_malloc((void **)&ids, sizeof(uint32_t) * (size_t)widest) != hipSuccess) {
             rc = fail(USPG_E_NOMEM, "segment colouring: allocation failed");
             break;
         }
@@ -354,7 +354,7 @@ int colour_segments(uspg_coeffs *c, hipStream_t s)
         if (!keep) c->view_rowptr.release();
     } while (0);
     (void)hipStreamSynchronize(s);
-    (void)hipFree(cnt); (void)hipFree(ids); (void)hipFree(mark);
+    (void)dev_free(cnt); (void)dev_free(ids); (void)dev_free(mark);
     if (rc != USPG_OK) return rc;
     return choose_lattice(c);
 }

@@ -421,7 +421,7 @@ int uspg_build_slabs(const uspg_coeffs *c, int32_t n_slabs, void *stream, uspg_s
     const int nz = c->g->nz;
     if (n_slabs < 1 || n_slabs > nz || n_slabs > USPG_MAX_SLABS)
         return fail(USPG_E_ARG, "n_slabs must lie in [1, min(n_slices, USPG_MAX_SLABS)]");
-    int rc = check_device(c->device);
+    int rc = check_coeffs(c);
     if (rc != USPG_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     auto *S = new uspg_slabs();

@@ -93,29 +93,28 @@ TraceGeo trace_geo(const uspg_coeffs *c)
     return G;
 }
 
-int trace_reference_view(uspg_coeffs *c, hipStream_t s)
+int trace_count_rows(uspg_coeffs *c, hipStream_t s)
 {
-    const uspg_scan_desc &sc = c->scan;
     const TraceGeo G = trace_geo(c);
-
+    if (!G.kq || !G.hq) return fail(USPG_E_INTERNAL, "trace: layout tables not on the device");
     const int64_t nrays = c->nrays;
     const unsigned blocks = (unsigned)((nrays + 255) / 256);
-    uint32_t *cnt = nullptr;
-    unsigned int *mx = nullptr;
-    USPG_HIP(hipMalloc((void **)&cnt, sizeof(uint32_t) * (nrays + 1)));
-    USPG_HIP(hipMalloc((void **)&mx, sizeof(unsigned int)));
     int rc = USPG_OK;
+    DevBuf rp, mx;
     do {
+        if ((rc = c->pend_cnt.alloc(sizeof(uint32_t) * (nrays + 1))) != USPG_OK) break;
+        if ((rc = rp.alloc(sizeof(int64_t) * (nrays + 1))) != USPG_OK) break;
+        if ((rc = mx.alloc(sizeof(unsigned int))) != USPG_OK) break;
+        uint32_t *cnt = c->pend_cnt.as<uint32_t>();
         hipLaunchKernelGGL(trace_count, dim3(blocks), dim3(256), 0, s, G, nrays, cnt);
         if (hipGetLastError() != hipSuccess) { rc = fail(USPG_E_HIP, "trace_count launch failed"); break; }
-        if ((rc = c->rowptr.alloc(sizeof(int64_t) * (nrays + 1))) != USPG_OK) break;
-        if ((rc = exclusive_scan_u32_to_i64(cnt, c->rowptr.as<int64_t>(), nrays, s)) != USPG_OK) break;
-        if (hipMemsetAsync(mx, 0, sizeof(unsigned int), s) != hipSuccess) { rc = fail(USPG_E_HIP, "memset"); break; }
-        hipLaunchKernelGGL(row_lengths_max, dim3(blocks), dim3(256), 0, s, cnt, nrays, mx);
+        if ((rc = exclusive_scan_u32_to_i64(cnt, rp.as<int64_t>(), nrays, s)) != USPG_OK) break;
+        if (hipMemsetAsync(mx.p, 0, sizeof(unsigned int), s) != hipSuccess) { rc = fail(USPG_E_HIP, "memset"); break; }
+        hipLaunchKernelGGL(row_lengths_max, dim3(blocks), dim3(256), 0, s, cnt, nrays, mx.as<unsigned int>());
         int64_t nnz = 0;
         unsigned int mrow = 0;
-        if (hipMemcpyAsync(&nnz, c->rowptr.as<int64_t>() + nrays, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipMemcpyAsync(&mrow, mx, sizeof(unsigned int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        if (hipMemcpyAsync(&nnz, rp.as<int64_t>() + nrays, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&mrow, mx.p, sizeof(unsigned int), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             rc = fail(USPG_E_HIP, "trace: reading the row count failed");
             break;
@@ -123,6 +122,23 @@ int trace_reference_view(uspg_coeffs *c, hipStream_t s)
         if (nnz >= (int64_t)UINT32_MAX) { rc = fail(USPG_E_ARG, "more than 2^32 reference coefficients"); break; }
         c->nnz = nnz;
         c->max_row = (int32_t)mrow;
+    } while (0);
+    if (rc != USPG_OK) c->pend_cnt.release();
+    return rc;
+}
+
+int trace_fill_rows(uspg_coeffs *c, hipStream_t s)
+{
+    const uspg_scan_desc &sc = c->scan;
+    const TraceGeo G = trace_geo(c);
+    if (!G.kq || !G.hq || !c->pend_cnt.p || !c->rowptr.p || !c->coef.p)
+        return fail(USPG_E_INTERNAL, "trace: tables, counts or rows not on the device");
+    const int64_t nrays = c->nrays, nnz = c->nnz;
+    const unsigned blocks = (unsigned)((nrays + 255) / 256);
+    int rc = USPG_OK;
+    do {
+        if ((rc = exclusive_scan_u32_to_i64(c->pend_cnt.as<uint32_t>(), c->rowptr.as<int64_t>(), nrays, s)) != USPG_OK)
+            break;
         // the walk writes ids and coefficients as two arrays, then they are
         // interleaved into the (id, coefficient) pairs the kernels read
         const bool f64 = sc.coeff_dtype == USPG_F64;
@@ -130,12 +146,7 @@ int trace_reference_view(uspg_coeffs *c, hipStream_t s)
         const int64_t n1 = nnz > 0 ? nnz : 1;
         DevBuf ids, a;
         if ((rc = ids.alloc(sizeof(uint32_t) * n1)) != USPG_OK) break;
-        if ((rc = a.alloc(asz * n1)) != USPG_OK) { ids.release(); break; }
-        if ((rc = c->coef.alloc((f64 ? sizeof(Coef<double>) : sizeof(Coef<float>)) * n1)) != USPG_OK) {
-            ids.release();
-            a.release();
-            break;
-        }
+        if ((rc = a.alloc(asz * n1)) != USPG_OK) break;
         int binary = sc.weights == USPG_WEIGHTS_BINARY;
         const unsigned eb = (unsigned)((n1 + 255) / 256);
         if (f64) {
@@ -151,13 +162,9 @@ int trace_reference_view(uspg_coeffs *c, hipStream_t s)
         }
         const bool launched = hipGetLastError() == hipSuccess;
         const bool synced = hipStreamSynchronize(s) == hipSuccess;
-        ids.release();
-        a.release();
         if (!launched) { rc = fail(USPG_E_HIP, "trace_fill launch failed"); break; }
         if (!synced) { rc = fail(USPG_E_HIP, "trace_fill failed"); break; }
     } while (0);
-    (void)hipFree(cnt);
-    (void)hipFree(mx);
     return rc;
 }
 

@@ -37,13 +37,39 @@ template <> struct alignas(16) Coef<double> {
     double a;
 };
 
-// Device buffer owned by a handle.
+// Counted device allocation and release (every library allocation).
+hipError_t dev_malloc(void **p, size_t n);
+hipError_t dev_free(void *p);
+
+// Device buffer of a handle: allocated by the library (owned) or a piece of
+// a caller's work space (borrowed, never freed here).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = true;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
     int alloc(size_t n);
+    void borrow(void *q, size_t n)
+    {
+        release();
+        p = q;
+        bytes = n;
+        owned = false;
+    }
     void release();
     template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Carves 256-byte aligned buffers out of a caller's work space, or only adds
+// up their sizes when base is null.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, off = 0;
+    static size_t rounded(size_t n) { return ((n ? n : 1) + 255) / 256 * 256; }
+    int take(DevBuf &b, size_t n);
 };
 
 }  // namespace uspg
@@ -115,6 +141,13 @@ struct uspg_coeffs {
     uspg::DevBuf d_colid;         // uint32 [records]: slice-0 cell id of each piece
     uspg::DevBuf d_codes;         // RayCode [nrays]
     uspg::DevBuf d_words;         // uint64: piece / slice bits of the coded rays
+    // Two-call build: after the size query the handle is pending (counts
+    // only) until a second call fills the caller's work space.
+    bool pending = false;
+    bool want_codes = false;
+    size_t ws_needed = 0;
+    uspg::DevBuf pend_cnt;        // uint32 [nrays + 1]: entries per ray (library memory, until the fill)
+    int64_t pend_nrec = 0, pend_nwords = 0;
 };
 
 namespace uspg {
@@ -131,8 +164,10 @@ inline int32_t stored_coeff_dtype(const uspg_coeffs *c) { return c->segments ? (
 // Rings per group of the blocked device layout.
 constexpr int kRingGroup = 4;
 
-// trace.hip
-int trace_reference_view(uspg_coeffs *c, hipStream_t s);
+// trace.hip: the count pass (pend_cnt, nnz, max_row) and the fill pass
+// (into rowptr and coef, already set).
+int trace_count_rows(uspg_coeffs *c, hipStream_t s);
+int trace_fill_rows(uspg_coeffs *c, hipStream_t s);
 // colour.hip
 int colour_reference_view(uspg_coeffs *c, hipStream_t s);
 // ORs into mark (device, det_u * det_v bytes) the offsets of every pair of
@@ -146,15 +181,18 @@ int choose_lattice(uspg_coeffs *c);
 int segments_reference_view(uspg_coeffs *c, hipStream_t s);
 int colour_segments(uspg_coeffs *c, hipStream_t s);
 int segments_row(const uspg_coeffs *c, int view, int64_t ray, std::vector<int64_t> &cells);
-// coded.hip: coded rows of a cone-beam coefficient set (after tracing)
-int build_row_codes(uspg_coeffs *c, hipStream_t s);
+// coded.hip: coded rows of a cone-beam coefficient set: the sizes (after the
+// count pass: pend_nrec, pend_nwords) and the codes (after tracing, into
+// d_colptr, d_colt, d_colid, d_codes, d_words, already set).
+int code_count(uspg_coeffs *c, hipStream_t s);
+int code_fill(uspg_coeffs *c, hipStream_t s);
 // scan.hip
 int exclusive_scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, hipStream_t s);
 int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s);
 // mart.hip
 int mart_launch(const uspg_coeffs *c, int dtype, const void *proj, void *image, void *work,
                 int n_sweeps, double beta, double tol, int32_t *sweeps_done, hipStream_t s);
-int mart_timing(int enable, double *batch_ms, int64_t *batch_launches);
+int mart_timing(int enable, hipStream_t s, double *batch_ms, int64_t *batch_launches);
 // Whether batch timing is on, and adding a timed run of launches to it.
 bool stream_capturing(hipStream_t s);
 // Whether coefficient loads take the non-temporal hint: true unless the
@@ -170,7 +208,7 @@ struct UntimedScope {
     UntimedScope();
     ~UntimedScope();
 };
-void mart_timing_add(int64_t ns, int64_t launches);
+void mart_timing_add(hipStream_t s, int64_t ns, int64_t launches);
 // One (view, class) batch of the single-problem kernel over explicit rows
 // of (id, coefficient) pairs of float coefficients (shift added mod wtot);
 // nch bounds the register path from the longest row.
@@ -192,6 +230,8 @@ int layout_permute(const uspg_coeffs *c, int dtype, const void *src, void *dst, 
                    hipStream_t s);
 // api.hip
 int check_device(int want);
+// A built (not pending) coefficient handle on the current device.
+int check_coeffs(const uspg_coeffs *c);
 int current_device_id(int *dev);
 // remap.hip
 int remap_launch(const uspg_grid *g, int dtype, const void *image, void *cart, int nc, int mode,

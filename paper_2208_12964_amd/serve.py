@@ -76,12 +76,14 @@ def footprint_bytes(coeffs: Coeffs, proj: torch.Tensor, dtype) -> int:
 
 class Admission:
     """Admission by device-memory footprint, first come first served within
-    each lane.  A queued request is admitted when it fits the remaining
-    budget and its lane has a free slot.  A request waiting for a slot holds
-    back only later requests of its own lane.  A request waiting for memory
-    may be passed by later ones that fit (`skip_ahead`) until it has waited
-    `max_wait` seconds; from then on nothing behind it is admitted, so the
-    memory it needs drains free.  A request larger than the whole budget is
+    each lane.  The budget covers the resident coefficient sets (`reserve`,
+    held until the server ends) and the admitted requests.  A queued request
+    is admitted when it fits what the budget has left and its lane has a
+    free slot.  A request waiting for a slot holds back only later requests
+    of its own lane.  A request waiting for memory may be passed by later
+    ones that fit (`skip_ahead`) until it has waited `max_wait` seconds; from
+    then on nothing behind it is admitted, so the memory it needs drains
+    free.  A request larger than the budget left after the resident sets is
     rejected."""
 
     def __init__(self, budget: int, skip_ahead: bool = True, max_wait: float = 1.0):
@@ -89,6 +91,12 @@ class Admission:
         self.skip_ahead = skip_ahead
         self.max_wait = max_wait
         self.in_use = 0
+        self.resident = 0
+
+    def reserve(self, nbytes: int):
+        """Charges a resident coefficient set to the budget for good."""
+        self.resident += nbytes
+        self.in_use += nbytes
 
     def pick(self, queue, now: float, free_slots) -> tuple:
         """Returns (admitted, rejected) lists; removes both from `queue`.
@@ -97,7 +105,7 @@ class Admission:
         held_lanes = set()     # lanes whose earlier request is still queued
         blocked = False        # a starved request holds back everything after it
         for r in queue:
-            if r.footprint > self.budget:
+            if r.footprint > self.budget - self.resident:
                 rejected.append(r)
                 continue
             if blocked or r.lane in held_lanes:
@@ -145,7 +153,8 @@ class _Lane:
 
 class Server:
     """Continuous-batching server.  `geometry(key) -> (Grid, Coeffs)`;
-    `lane_of(key) -> int`; `budget` bytes for admitted requests; at most
+    `lane_of(key) -> int`; `budget` bytes for the resident coefficient sets
+    and the admitted requests together; at most
     `max_slots` requests per lane (an int, or a dict lane -> count with 64
     for lanes it does not name); each step call advances a lane by at most
     `steps_per_call` steps; at most `depth` calls per lane are in flight.
@@ -178,7 +187,10 @@ class Server:
         return self.lanes[lid]
 
     def prepare(self, r: Request):
+        fresh = r.key not in self.cache.entries
         _, co = self.cache.get(r.key)
+        if fresh:    # a new resident coefficient set (its work space) counts in the budget
+            self.admission.reserve(co.device_bytes)
         r.lane = self.lane_of(r.key)
         self._lane(r.lane)
         r.footprint = footprint_bytes(co, r.proj, self.dtype)

@@ -141,3 +141,26 @@ def test_binding_refuses_short_buffers(U):
     eng.close()
     with pytest.raises(ValueError):
         U.Slabs(co, 1).run(proj[:-1], img, 1, 0.1)
+
+
+def test_timing_is_per_stream(U):
+    # batch timing is kept per stream: a solve on another stream neither adds
+    # to it nor turns it off
+    w = synth.small_cone("t-cone", n_rings=8, n_views=4, det=12, m=4, sweeps=2)
+    g = U.Grid.from_workload(w)
+    co = U.Coeffs.from_workload(g, w)
+    P = torch.as_tensor(synth.make_projections(w), dtype=torch.float32, device=dev()).contiguous()
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    U.mart_timing(True, stream=a)
+    img_b = torch.ones(g.n_cells, device=dev())
+    with torch.cuda.stream(b):
+        U.mart(co, P, img_b, w.sweeps, w.beta, stream=b)
+    b.synchronize()
+    assert U.mart_timing(True, stream=a)[1] == 0         # nothing on a yet (and reset)
+    img_a = torch.ones(g.n_cells, device=dev())
+    with torch.cuda.stream(a):
+        U.mart(co, P, img_a, w.sweeps, w.beta, stream=a)
+    a.synchronize()
+    ms, n = U.mart_timing(False, stream=a)
+    assert n == w.sweeps * w.n_views * co.lattice[0] * co.lattice[1] and ms > 0
+    assert torch.equal(img_a, img_b)

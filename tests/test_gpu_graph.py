@@ -44,10 +44,11 @@ def test_captured_mart_run_replays_equal_eager(U, kind, dtype):
 
     img = torch.ones(grid.n_cells, dtype=dtype, device=dev)
     work = torch.empty(co.workspace_bytes(dtype), dtype=torch.uint8, device=dev)
-    U.mart_timing(True)
     g = torch.cuda.CUDAGraph()
     cart = torch.empty_like(cart_eager)
     with torch.cuda.graph(g):
+        cs = torch.cuda.current_stream()                 # the capturing stream
+        U.mart_timing(True, stream=cs)
         U.mart(co, proj, img, w.sweeps, w.beta, work=work)
         U.to_cartesian(grid, img, nc, out=cart)
     torch.cuda.synchronize()
@@ -60,7 +61,7 @@ def test_captured_mart_run_replays_equal_eager(U, kind, dtype):
         assert torch.equal(img, eager), (kind, rep)
         assert torch.equal(cart, cart_eager), (kind, rep)
         assert torch.isfinite(junk)
-    _, launches = U.mart_timing(False)
+    _, launches = U.mart_timing(False, stream=cs)
     assert launches == 0                                 # the captured call was not timed
     del g
 

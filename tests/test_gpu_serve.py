@@ -164,17 +164,19 @@ def test_server_results_equal_alone_and_oracle(U):
 
     projs = [synth.make_projections_torch(it.workload(), dev, torch.float32).reshape(-1) for it in items]
     reqs = [Request(it.k, it.arrival, it.key, pr, it.sweeps, 0.1) for it, pr in zip(items, projs)]
-    # budget: about three of the largest requests at once, so admission waits
+    # budget: the resident coefficient sets (charged as their geometries are
+    # built) plus about three of the largest requests at once, so admission waits
     srv = Server(geometry, budget=1, steps_per_call=5)
     for r in reqs:
         srv.prepare(r)
-    srv.admission.budget = 3 * max(r.footprint for r in reqs)
+    assert srv.admission.resident == sum(co.device_bytes for _, co in geo.values()) > 0
+    srv.admission.budget = srv.admission.resident + 3 * max(r.footprint for r in reqs)
     cancelled = reqs[5]
     assert srv.cancel(cancelled)
     stats = srv.run(reqs)
     srv.close()
     assert stats["completed"] == len(reqs) - 1 and stats["rejected"] == 0
-    assert stats["p99_s"] >= stats["p50_s"] > 0 and srv.admission.in_use == 0
+    assert stats["p99_s"] >= stats["p50_s"] > 0 and srv.admission.in_use == srv.admission.resident
     assert cancelled.image is None and cancelled.t_done is None
     fifo_reqs = [Request(r.k, r.arrival, r.key, r.proj, r.sweeps, r.beta) for r in reqs]
     fifo = serve_fifo(geometry, fifo_reqs)

@@ -85,6 +85,18 @@ def test_admission_rejects_oversized():
     assert [r.k for r in rej] == [0] and [r.k for r in got] == [1] and not q
 
 
+def test_admission_counts_resident_coefficients():
+    # resident coefficient sets take their share of the budget for good
+    adm = Admission(100, skip_ahead=False)
+    adm.reserve(30)
+    q = deque([_req(0, 0.0, 71), _req(1, 0.0, 40), _req(2, 0.0, 40)])
+    got, rej = adm.pick(q, 0.0, {0: 8})
+    assert [r.k for r in rej] == [0]                   # more than the 70 left after the resident sets
+    assert [r.k for r in got] == [1] and [r.k for r in q] == [2] and adm.in_use == 70
+    adm.release(got[0])
+    assert adm.in_use == 30                            # the resident share stays
+
+
 def test_percentile_nearest_rank():
     xs = list(range(1, 201))
     assert percentile(xs, 50) == 100 and percentile(xs, 99) == 198 and percentile(xs, 100) == 200
