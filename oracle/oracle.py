@@ -22,22 +22,32 @@ RULE = {"paper": 0, "multiple": 1, "explicit": 2}
 _lib = None
 
 
-def build_oracle(force: bool = True) -> str:
-    """Compile the oracle shared library with gcc (OpenMP, -O2, IEEE math)."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-               "-Wno-unused-function", _SRC, "-o", _LIB + ".tmp", "-lm"]
+# gcc flags of a build with AddressSanitizer and UndefinedBehaviorSanitizer
+# (host code only; the tests load such a build with the ASan runtime preloaded)
+SANITIZE = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+            "-fno-omit-frame-pointer"]
+
+
+def build_oracle(force: bool = True, out: str | None = None, sanitize: bool = False) -> str:
+    """Compile the oracle shared library with gcc (OpenMP, -O2, IEEE math);
+    `sanitize` builds it with the sanitizers into `out` instead."""
+    out = out or _LIB
+    if force or not os.path.exists(out):
+        opt = SANITIZE if sanitize else ["-O2"]
+        cmd = ["gcc", *opt, "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               "-Wno-unused-function", _SRC, "-o", out + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(out + ".tmp", out)
+    return out
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    # USPG_ORACLE_LIB points the tests at a deliberately broken oracle build
-    # (mutation checks of the pins); never set in normal runs.
+    # USPG_ORACLE_LIB points the tests at another oracle build: a deliberately
+    # broken one (mutation checks of the pins) or a sanitized one; never set
+    # in normal runs.
     path = os.environ.get("USPG_ORACLE_LIB", _LIB)
     if not os.path.exists(path):
         raise RuntimeError(f"oracle library missing: {path} (run __graft_entry__.build())")

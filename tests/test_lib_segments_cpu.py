@@ -12,6 +12,7 @@ import pytest
 
 import synth
 from oracle import Oracle
+from oracle.oracle import SANITIZE
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 BUILD = os.path.join(HERE, "_build")
@@ -21,8 +22,11 @@ GEOM = {"parallel2d": 0, "fan2d": 1, "cone3d": 2}
 @pytest.fixture(scope="module")
 def hs():
     os.makedirs(BUILD, exist_ok=True)
-    so = os.path.join(BUILD, "host_segments.so")
-    subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+    # USPG_HOST_SANITIZE=1: the build with the sanitizers (test_sanitizers.py)
+    san = os.environ.get("USPG_HOST_SANITIZE") == "1"
+    so = os.path.join(BUILD, "host_segments" + ("_asan" if san else "") + ".so")
+    opt = SANITIZE if san else ["-O2"]
+    subprocess.run(["g++", *opt, "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
                     "-Wno-unknown-pragmas", os.path.join(HERE, "host_segments.cpp"), "-o", so], check=True)
     L = C.CDLL(so)
     L.hs_setup.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_int, C.c_int, C.c_int,

@@ -11,6 +11,7 @@ import pytest
 
 import synth
 from oracle import Oracle
+from oracle.oracle import SANITIZE
 from rowcmp import LEN_ATOL, LEN_RTOL, compare_rows, on_axis
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -21,8 +22,11 @@ GEOM = {"parallel2d": 0, "fan2d": 1, "cone3d": 2}
 @pytest.fixture(scope="module")
 def hw():
     os.makedirs(BUILD, exist_ok=True)
-    so = os.path.join(BUILD, "host_walk.so")
-    subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+    # USPG_HOST_SANITIZE=1: the build with the sanitizers (test_sanitizers.py)
+    san = os.environ.get("USPG_HOST_SANITIZE") == "1"
+    so = os.path.join(BUILD, "host_walk" + ("_asan" if san else "") + ".so")
+    opt = SANITIZE if san else ["-O2"]
+    subprocess.run(["g++", *opt, "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
                     "-Wno-unknown-pragmas", os.path.join(HERE, "host_walk.cpp"), "-o", so], check=True)
     L = C.CDLL(so)
     L.hw_setup.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_int, C.c_int,
