@@ -113,3 +113,40 @@ def test_graph_replays_match_eager(U):
             U.mart(co, proj, img, s_, w.beta)
             assert torch.equal(img, m), rep
         assert torch.isfinite(junk)
+
+
+def test_batch_configuration_sizes_equal_oracle(U):
+    # slices of the batched workload's largest sizes (Nr 128 and 256, 32 views
+    # over a half turn, 2 Nr bins, sector multiple 2p, 15 sweeps): their rows
+    # run past 8 chunks of 64 entries, so the lockstep and persistent kernels
+    # take their 16-chunk register bodies; every image equals the problem
+    # alone and the FP64 oracle within 1e-4
+    dev = torch.device("cuda:0")
+    ws = [synth.parallel(f"bs{k}", nr, 32, 2 * nr, 64, phantom="ellipses", n_objects=6, seed=4100 + k,
+                         sweeps=15, beta=0.1, dtype="f32")
+          for k, nr in enumerate((256, 128, 256, 64))]
+    print("case batch configuration sizes", [w.name for w in ws], flush=True)
+    grids = [U.Grid.from_workload(w) for w in ws]
+    cos = [U.Coeffs.from_workload(g, w) for g, w in zip(grids, ws)]
+    assert max(co.max_row for co in cos) > 8 * 64            # the 16-chunk bodies
+    Ps = [synth.make_projections(w) for w in ws]
+    projs = [torch.as_tensor(P, dtype=torch.float32, device=dev).contiguous() for P in Ps]
+    alone = []
+    for co, proj, w, g in zip(cos, projs, ws, grids):
+        img = torch.ones(g.n_cells, device=dev)
+        U.mart(co, proj, img, w.sweeps, w.beta)
+        alone.append(img)
+    b = U.Batch(cos)
+    for mode, block, lds in (("lockstep", 256, False), ("persistent", 1024, True)):
+        b.set(mode, block, lds)
+        imgs = [torch.ones(g.n_cells, device=dev) for g in grids]
+        b.run(projs, imgs, [w.sweeps for w in ws], [w.beta for w in ws])
+        torch.cuda.synchronize()
+        for a, m in zip(alone, imgs):
+            assert torch.equal(a, m), mode
+    for w, P, img in zip(ws, Ps, alone):
+        f_ref, _, _ = Oracle(w, nthreads=NTHREADS).reconstruct(P)
+        f = img.cpu().numpy().astype(np.float64)
+        err = np.max(np.abs(f - f_ref)) / np.max(np.abs(f_ref))
+        print(f"{w.name} (Nr {w.n_rings}): err_inf {err:.2e}")
+        assert err <= 1e-4, w.name

@@ -116,6 +116,47 @@ def test_engine_wide_problems_equal_alone(U, dtype):
         assert torch.equal(a, m), ws[i].name
 
 
+def test_engine_128_ring_cone_requests_equal_oracle(U):
+    # two 128-ring cone requests (fewer rays per class than fill the chip, so
+    # they share the lockstep launch, whose rows of up to 8 chunks take its
+    # 8-chunk body) admitted at different steps beside a small one: each
+    # result equals the request alone and the FP64 oracle within 1e-4
+    dev = torch.device("cuda:0")
+    ws = [synth.serve_request(21, 128, 8, 3), synth.serve_request(22, 128, 16, 2),
+          synth.serve_request(23, 16, 8, 3)]
+    print("case 128-ring engine", [w.name for w in ws], flush=True)
+    grids = [U.Grid.from_workload(w) for w in ws]
+    cos = [U.Coeffs.from_workload(g, w) for g, w in zip(grids, ws)]
+    assert 5 * 64 < max(co.max_row for co in cos[:2]) <= 8 * 64
+    Ps = [synth.make_projections(w) for w in ws]
+    projs = [torch.as_tensor(P, dtype=torch.float32, device=dev).reshape(-1).contiguous() for P in Ps]
+    alone = []
+    for co, proj, w, g in zip(cos, projs, ws, grids):
+        img = torch.ones(g.n_cells, device=dev)
+        U.mart(co, proj, img, w.sweeps, w.beta)
+        alone.append(img)
+    eng = U.Engine(4)
+    imgs = [torch.ones(g.n_cells, device=dev) for g in grids]
+    slot_of = {eng.admit(cos[0], projs[0], imgs[0], ws[0].sweeps, ws[0].beta): 0}
+    finished = []
+    for s in eng.step(11):
+        finished.append(slot_of.pop(s))
+    for i in (1, 2):
+        slot_of[eng.admit(cos[i], projs[i], imgs[i], ws[i].sweeps, ws[i].beta)] = i
+    while slot_of:
+        for s in eng.step(13):
+            finished.append(slot_of.pop(s))
+    torch.cuda.synchronize()
+    assert sorted(finished) == [0, 1, 2]
+    for i, (a, m) in enumerate(zip(alone, imgs)):
+        assert torch.equal(a, m), ws[i].name
+        f_ref, _, _ = Oracle(ws[i], nthreads=NTHREADS).reconstruct(Ps[i])
+        err = rel_err(m.cpu().numpy().astype(np.float64), f_ref)
+        print(f"{ws[i].name}: err_inf {err:.2e}")
+        assert err <= 1e-4, ws[i].name
+    eng.close()
+
+
 def test_engine_errors(U):
     dev = torch.device("cuda:0")
     w = problems()[0]
@@ -149,7 +190,8 @@ def _serve_requests(dev, n=14, seed=8):
     return items
 
 
-def test_server_results_equal_alone_and_oracle(U):
+@pytest.mark.parametrize("shared_stream", [False, True], ids=["lane-streams", "shared-stream"])
+def test_server_results_equal_alone_and_oracle(U, shared_stream):
     from paper_2208_12964_amd.serve import Request, Server, serve_fifo
 
     dev = torch.device("cuda:0")
@@ -166,7 +208,7 @@ def test_server_results_equal_alone_and_oracle(U):
     reqs = [Request(it.k, it.arrival, it.key, pr, it.sweeps, 0.1) for it, pr in zip(items, projs)]
     # budget: the resident coefficient sets (charged as their geometries are
     # built) plus about three of the largest requests at once, so admission waits
-    srv = Server(geometry, budget=1, steps_per_call=5)
+    srv = Server(geometry, budget=1, steps_per_call=5, shared_stream=shared_stream)
     for r in reqs:
         srv.prepare(r)
     assert srv.admission.resident == sum(co.device_bytes for _, co in geo.values()) > 0
