@@ -83,13 +83,15 @@ def parse():
     ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=120.0, help="serve: arrival window (s)")
     ap.add_argument("--budget-gib", type=float, default=16.0, help="serve: admission budget (GiB)")
-    ap.add_argument("--steps-per-call", type=int, default=64, help="serve: engine steps per call")
-    ap.add_argument("--lanes", default="rings", choices=["rings", "one"],
-                    help="serve: one engine per ring count, or a single engine")
-    ap.add_argument("--slots", default="256:2,128:8,64:32",
-                    help="serve: slots per lane as lane:count pairs (lane = ring count with --lanes rings)")
+    ap.add_argument("--steps-per-call", type=int, default=128, help="serve: engine steps per call")
+    ap.add_argument("--lanes", default="split", choices=["rings", "split", "one"],
+                    help="serve: one engine per ring count; the 256-ring requests (whose steps fill the "
+                         "chip alone) in one engine and the rest in engine 0; or a single engine")
+    ap.add_argument("--slots", default="256:2,0:40",
+                    help="serve: slots per lane as lane:count pairs (lane = ring count with --lanes rings; "
+                         "256 and 0 with --lanes split; 0 with --lanes one)")
     ap.add_argument("--fifo", action="store_true", help="serve: also run the one-at-a-time baseline")
-    ap.add_argument("--streams", default="lane", choices=["lane", "shared"],
+    ap.add_argument("--streams", default="shared", choices=["lane", "shared"],
                     help="serve: one stream per lane (calls of different lanes overlap) or one shared stream")
     return ap.parse_args()
 
@@ -275,7 +277,8 @@ def bench_serve(args):
     rays.clear()
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
-    lane_of = (lambda key: key[0]) if args.lanes == "rings" else (lambda key: 0)
+    lane_of = {"rings": lambda key: key[0], "split": lambda key: key[0] if key[0] >= 256 else 0,
+               "one": lambda key: 0}[args.lanes]
 
     def make(_items):
         return [Request(it.k, it.arrival, it.key, pr, it.sweeps, 0.1) for it, pr in zip(items, projs)]
@@ -310,6 +313,8 @@ def bench_serve(args):
            "build_s": build_s, "input_generation_s": gen_s, "coeff_gib_resident": coeff_bytes / 2**30}
     if args.fifo:
         say("serve: one-at-a-time baseline")
+        torch.cuda.synchronize()
+        time.sleep(1.0)    # an idle second parts the two phases in a kernel trace
         fst = serve_fifo(geo.get, make(items), keep_results=False,
                          progress=lambda s: say("fifo: t=%.0f s completed %d" % (s["wall_s"], s["completed"])))
         out["one_at_a_time"] = fst

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "mart_coded.hpp"
 #include "mart_row.hpp"
 #include "uspg_internal.hpp"
 
@@ -37,6 +38,7 @@ struct uspg_batch {
     size_t lds_bytes = 0;         // dynamic LDS of the launch
     int maxc = 16;
     bool any_kept = false;        // some problem runs kept per-view rows
+    bool any_coded = false;       // some problem has coded rows
     bool nt = true;               // lockstep coefficient loads with the non-temporal hint
     std::vector<int> lds_mode;    // per problem
     // lockstep
@@ -51,6 +53,10 @@ struct uspg_batch {
 };
 
 namespace uspg {
+
+// The codes of a coefficient set for the batch kernels (mart.hip).
+batchk::CodeTab code_tab(const uspg_coeffs *c);
+
 namespace {
 
 using row::mart_row;
@@ -64,7 +70,17 @@ struct ProblemStatic {
     uint32_t Wc, Wtot;
     int U, Ku, Kv, n_views, lds;
     const int64_t *view_start;  // kept per-view rows: first entry of each view; null: shifted reference rows
+    batchk::CodeTab K;          // coded rows (K.codes null: none)
 };
+
+// Row forms of a lockstep launch: stored shifted rows only, some kept
+// per-view rows, or some coded rows (read through the codes; the other
+// problems' stored rows as usual).
+constexpr int kRowsStored = 0, kRowsKept = 1, kRowsCoded = 2;
+
+// Class rows per band of the ray order for coded problems (as in the
+// single-problem coded kernel).
+constexpr int kLockstepBand = 8;
 
 // Rows of view v: the reference rows with the cell ids shifted by v Wc
 // (v < n_views <= q, so v Wc < Wtot), or the view's own kept rows (no
@@ -153,10 +169,13 @@ __global__ void mart_multi(MultiArgs<T> A)
 // prefix range holds it; its wavefronts take that problem's rays of the
 // current (view, class) in order.  (Capping this grid and striding, as the
 // single-problem batch kernel does, made it 6-42 % slower.)
-template <class T, class TC, int MAXC, bool KEPT, bool NT>
+template <class T, class TC, int MAXC, int ROWS, bool NT>
 __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, const ProblemDyn<T> *dyn,
                                                      const int *wgbeg, int n, int step)
 {
+    constexpr bool KEPT = ROWS == kRowsKept;
+    // slice bounds of a coded ray, one table per wavefront (at most 4)
+    __shared__ double planes[ROWS == kRowsCoded ? 4 : 1][ROWS == kRowsCoded ? coded::kMaxPlanes + 2 : 1];
     // each XCD takes a contiguous run of the virtual workgroups, as in the
     // single-problem kernel
     const int b = row::xcd_block(blockIdx.x, gridDim.x);
@@ -178,7 +197,28 @@ __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, co
     const int nw = ((int)(S.nrays / S.U) - cw + S.Kv - 1) / S.Kv;
     const int x = (b - wgbeg[lo]) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (x >= nu * nw) return;
-    const int64_t r = (int64_t)(cw + (x / nu) * S.Kv) * S.U + cu + (x % nu) * S.Ku;
+    int64_t r = (int64_t)(cw + (x / nu) * S.Kv) * S.U + cu + (x % nu) * S.Ku;
+    if constexpr (ROWS == kRowsCoded) {
+        if (S.K.codes) {
+            // the coded kernel's band order (bands of kLockstepBand class
+            // rows, w fastest), so that rays in flight share their columns'
+            // in-plane paths; rays of one class are independent, so the
+            // order leaves the bits alone
+            const int wb = x / (kLockstepBand * nu);
+            const int xl = x - wb * kLockstepBand * nu;
+            const int h = nw - wb * kLockstepBand < kLockstepBand ? nw - wb * kLockstepBand : kLockstepBand;
+            r = (int64_t)(cw + (wb * kLockstepBand + xl % h) * S.Kv) * S.U + cu + (xl / h) * S.Ku;
+            const coded::RayCode rc = S.K.codes[r];
+            if (rc.n == 0) return;
+            if (rc.word >= 0) {   // rebuilt from the codes (same entries, same bits)
+                const uint32_t shift = (uint32_t)(((uint64_t)v * S.Wc) % S.Wtot);
+                batchk::coded_row_any<T, TC, MAXC>(S.K, D.f, shift, S.Wtot, D.beta, rc,
+                                                   D.P[(int64_t)v * S.nrays + r], threadIdx.x & 63,
+                                                   planes[threadIdx.x >> 6]);
+                return;
+            }
+        }
+    }
     const int64_t *rp = view_rowptr<KEPT>(S, v);
     const int64_t beg = rp[r];
     const int len = (int)(rp[r + 1] - beg);
@@ -192,7 +232,7 @@ __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, co
 // The step sequence is captured once into a graph (per step count and launch
 // shape) and replayed with one graph launch; the run arguments it reads live
 // in d_dyn, refreshed before every replay.
-template <class T, class TC, int MAXC, bool KEPT, bool NT>
+template <class T, class TC, int MAXC, int ROWS, bool NT>
 int lockstep_typed(uspg_batch *b, int steps, hipStream_t s)
 {
     const int grid = b->wgbeg[b->n];
@@ -208,7 +248,7 @@ int lockstep_typed(uspg_batch *b, int steps, hipStream_t s)
             rc = fail(USPG_E_HIP, "hipStreamBeginCapture failed");
         } else {
             for (int t = 0; t < steps; ++t)
-                hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC, KEPT, NT>), dim3(grid), dim3(b->block), 0, cs,
+                hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC, ROWS, NT>), dim3(grid), dim3(b->block), 0, cs,
                                    b->d_static.as<ProblemStatic>(), b->d_dyn.as<ProblemDyn<T>>(),
                                    b->d_wgbeg.as<int>(), b->n, t);
             if (hipStreamEndCapture(cs, &b->graph) != hipSuccess ||
@@ -226,21 +266,26 @@ int lockstep_typed(uspg_batch *b, int steps, hipStream_t s)
     return USPG_OK;
 }
 
-template <class T, class TC, bool KEPT, bool NT>
+template <class T, class TC, int ROWS, bool NT>
 int lockstep_chunks(uspg_batch *b, int steps, hipStream_t s)
 {
-    if (b->maxc <= 2) return lockstep_typed<T, TC, 2, KEPT, NT>(b, steps, s);
-    if (b->maxc <= 4) return lockstep_typed<T, TC, 4, KEPT, NT>(b, steps, s);
-    if (b->maxc <= 8) return lockstep_typed<T, TC, 8, KEPT, NT>(b, steps, s);
-    return lockstep_typed<T, TC, 16, KEPT, NT>(b, steps, s);
+    if (b->maxc <= 2) return lockstep_typed<T, TC, 2, ROWS, NT>(b, steps, s);
+    if (b->maxc <= 4) return lockstep_typed<T, TC, 4, ROWS, NT>(b, steps, s);
+    if (b->maxc <= 8) return lockstep_typed<T, TC, 8, ROWS, NT>(b, steps, s);
+    return lockstep_typed<T, TC, 16, ROWS, NT>(b, steps, s);
 }
 
 template <class T, class TC>
 int lockstep_maxc(uspg_batch *b, int steps, hipStream_t s)
 {
     if (b->any_kept)
-        return b->nt ? lockstep_chunks<T, TC, true, true>(b, steps, s) : lockstep_chunks<T, TC, true, false>(b, steps, s);
-    return b->nt ? lockstep_chunks<T, TC, false, true>(b, steps, s) : lockstep_chunks<T, TC, false, false>(b, steps, s);
+        return b->nt ? lockstep_chunks<T, TC, kRowsKept, true>(b, steps, s)
+                     : lockstep_chunks<T, TC, kRowsKept, false>(b, steps, s);
+    if (b->any_coded)
+        return b->nt ? lockstep_chunks<T, TC, kRowsCoded, true>(b, steps, s)
+                     : lockstep_chunks<T, TC, kRowsCoded, false>(b, steps, s);
+    return b->nt ? lockstep_chunks<T, TC, kRowsStored, true>(b, steps, s)
+                 : lockstep_chunks<T, TC, kRowsStored, false>(b, steps, s);
 }
 
 template <class T, class TC, int MAXC, bool KEPT>
@@ -343,6 +388,7 @@ ProblemStatic static_of(const uspg_coeffs *c)
     p.Kv = c->Kv;
     p.n_views = c->scan.n_views;
     p.lds = 0;
+    p.K = kept ? batchk::CodeTab{} : code_tab(c);
     return p;
 }
 
@@ -360,6 +406,7 @@ int upload_static(uspg_batch *b)
     std::vector<ProblemStatic> st(b->n);
     b->lds_bytes = 0;
     b->any_kept = false;
+    b->any_coded = false;
     b->lds_mode.assign(b->n, 0);
     int maxrow = 0;
     for (int i = 0; i < b->n; ++i) {
@@ -372,6 +419,7 @@ int upload_static(uspg_batch *b)
         if (p.lds) b->lds_bytes = std::max(b->lds_bytes, need);
         maxrow = std::max(maxrow, (int)stored_max_row(c));
         b->any_kept = b->any_kept || kept_rows(c);
+        b->any_coded = b->any_coded || c->coded;
     }
     b->maxc = (maxrow + 63) / 64;
     // lockstep coefficient loads: non-temporal unless every coefficient set
@@ -493,12 +541,12 @@ int engine_upload(uspg_engine *e, hipStream_t s)
 // in order: the lockstep steps go first, then the steps of each wide
 // problem in one run, which keeps that problem's image in the caches
 // (two 256-ring problems alternating step by step took 10 % longer).
-template <class T, class TC, int MAXC, bool KEPT, bool NT>
+template <class T, class TC, int MAXC, int ROWS, bool NT>
 int engine_launch(uspg_engine *e, int steps, hipStream_t s)
 {
     if (!e->table.empty())
         for (int t = 0; t < steps; ++t)
-            hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC, KEPT, NT>), dim3(e->grid), dim3(64 * kEngineWaves), 0, s,
+            hipLaunchKernelGGL((mart_lockstep<T, TC, MAXC, ROWS, NT>), dim3(e->grid), dim3(64 * kEngineWaves), 0, s,
                                e->d_static.as<ProblemStatic>(), e->d_dyn.as<ProblemDyn<T>>(),
                                e->d_wgbeg.as<int>(), (int)e->table.size(), t);
     for (int id : e->wide) {
@@ -517,20 +565,20 @@ int engine_launch(uspg_engine *e, int steps, hipStream_t s)
     return USPG_OK;
 }
 
-template <class T, class TC, bool KEPT, bool NT>
+template <class T, class TC, int ROWS, bool NT>
 int engine_chunks(uspg_engine *e, int64_t chunks, int steps, hipStream_t s)
 {
-    if (chunks <= 2) return engine_launch<T, TC, 2, KEPT, NT>(e, steps, s);
-    if (chunks <= 4) return engine_launch<T, TC, 4, KEPT, NT>(e, steps, s);
-    if (chunks <= 8) return engine_launch<T, TC, 8, KEPT, NT>(e, steps, s);
-    return engine_launch<T, TC, 16, KEPT, NT>(e, steps, s);
+    if (chunks <= 2) return engine_launch<T, TC, 2, ROWS, NT>(e, steps, s);
+    if (chunks <= 4) return engine_launch<T, TC, 4, ROWS, NT>(e, steps, s);
+    if (chunks <= 8) return engine_launch<T, TC, 8, ROWS, NT>(e, steps, s);
+    return engine_launch<T, TC, 16, ROWS, NT>(e, steps, s);
 }
 
 template <class T, class TC>
 int engine_maxc(uspg_engine *e, int steps, hipStream_t s)
 {
     int64_t longest = 0;
-    bool kept = false;
+    bool kept = false, coded_any = false;
     // the lockstep launch reads every table problem's rows and image: the
     // coefficient loads keep the non-temporal hint unless they all fit the
     // last-level cache (each coefficient set counted once)
@@ -540,6 +588,7 @@ int engine_maxc(uspg_engine *e, int steps, hipStream_t s)
         const uspg_coeffs *c = e->slots[id].c;
         longest = std::max<int64_t>(longest, stored_max_row(c));
         kept = kept || kept_rows(c);
+        coded_any = coded_any || c->coded;
         if (std::find(sets.begin(), sets.end(), c) == sets.end()) {
             sets.push_back(c);
             coef_bytes += coef_set_bytes(c);
@@ -549,10 +598,13 @@ int engine_maxc(uspg_engine *e, int steps, hipStream_t s)
     const bool nt = stream_coefs(coef_bytes, image_bytes);
     const int64_t chunks = (longest + 63) / 64;
     if (kept)
-        return nt ? engine_chunks<T, TC, true, true>(e, chunks, steps, s)
-                  : engine_chunks<T, TC, true, false>(e, chunks, steps, s);
-    return nt ? engine_chunks<T, TC, false, true>(e, chunks, steps, s)
-              : engine_chunks<T, TC, false, false>(e, chunks, steps, s);
+        return nt ? engine_chunks<T, TC, kRowsKept, true>(e, chunks, steps, s)
+                  : engine_chunks<T, TC, kRowsKept, false>(e, chunks, steps, s);
+    if (coded_any)
+        return nt ? engine_chunks<T, TC, kRowsCoded, true>(e, chunks, steps, s)
+                  : engine_chunks<T, TC, kRowsCoded, false>(e, chunks, steps, s);
+    return nt ? engine_chunks<T, TC, kRowsStored, true>(e, chunks, steps, s)
+              : engine_chunks<T, TC, kRowsStored, false>(e, chunks, steps, s);
 }
 
 }  // namespace

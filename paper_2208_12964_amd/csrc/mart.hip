@@ -147,6 +147,23 @@ void launch_explicit(int nch, const CodedArgs<T, TC> &A, hipStream_t s)
     else hipLaunchKernelGGL((mart_explicit<T, TC, 32, NT>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
 }
 
+}  // namespace
+
+batchk::CodeTab code_tab(const uspg_coeffs *c)
+{
+    batchk::CodeTab K{};
+    if (!c->coded) return K;
+    K.codes = c->d_codes.as<coded::RayCode>();
+    K.words = c->d_words.as<uint64_t>();
+    K.t = c->d_colt.as<double>();
+    K.id0 = c->d_colid.as<uint32_t>();
+    K.Q = coded::CodeGeo{c->g->z0, c->g->h, c->g->nz, (uint32_t)c->Cq, (uint32_t)c->Wc};
+    K.binary = c->scan.weights == USPG_WEIGHTS_BINARY;
+    return K;
+}
+
+namespace {
+
 // Ray order of the coded kernel inside a class: bands of 8 class rows,
 // w fastest inside a band, so that the rays in flight on one XCD share
 // their columns' in-plane paths (cache-resident) while neighbouring columns
@@ -160,12 +177,7 @@ CodedArgs<T, TC> coded_args(const uspg_coeffs *c, const BatchArgs<T, TC> &B)
 {
     CodedArgs<T, TC> A{};
     A.B = B;
-    A.codes = c->d_codes.as<coded::RayCode>();
-    A.words = c->d_words.as<uint64_t>();
-    A.t = c->d_colt.as<double>();
-    A.id0 = c->d_colid.as<uint32_t>();
-    A.Q = coded::CodeGeo{c->g->z0, c->g->h, c->g->nz, (uint32_t)c->Cq, (uint32_t)c->Wc};
-    A.binary = c->scan.weights == USPG_WEIGHTS_BINARY;
+    A.K = code_tab(c);
     A.band = kCodedBand;
     return A;
 }

@@ -16,15 +16,20 @@
 namespace uspg {
 namespace batchk {
 
-template <class T, class TC>
-struct CodedArgs {
-    BatchArgs<T, TC> B;              // class, view, image, stored rows of explicit rays
+// The codes of one coefficient set (coded_rows.hpp).
+struct CodeTab {
     const coded::RayCode *codes;     // per ray
     const uint64_t *words;           // piece / slice bits, two words per 64 entries
     const double *t;                 // column records: piece starts
     const uint32_t *id0;             // column records: slice-0 cell ids
     coded::CodeGeo Q;
     int binary;
+};
+
+template <class T, class TC>
+struct CodedArgs {
+    BatchArgs<T, TC> B;              // class, view, image, stored rows of explicit rays
+    CodeTab K;
     int band;                        // ray order: bands of `band` class rows, w fastest inside a band
 };
 
@@ -33,15 +38,15 @@ struct CodedArgs {
 // code, so every chunk's table loads, then every gather, are issued before
 // the first wait.
 template <class T, class TC, int C>
-__device__ __forceinline__ void coded_row(const CodedArgs<T, TC> &A, const coded::RayCode &rc, T P, int lane,
-                                          double *planes)
+__device__ __forceinline__ void coded_row(const CodeTab &K, T *f, uint32_t shift, uint32_t wtot, T beta,
+                                          const coded::RayCode &rc, T P, int lane, double *planes)
 {
 #pragma clang fp contract(off)
     const int dk = coded::code_dk(rc), kinit = coded::code_kinit(rc), J = coded::code_planes(rc);
     // bounds of the slices the ray crosses, 0 .. J + 1 (t0, the J crossed
     // planes, then the next plane or t1); the previous ray of this
     // wavefront has finished reading the table
-    for (int j = lane; j <= J + 1; j += 64) planes[j] = coded::slice_bound(A.Q, kinit, dk, J, rc.t0, rc.t1, rc.ez, j);
+    for (int j = lane; j <= J + 1; j += 64) planes[j] = coded::slice_bound(K.Q, kinit, dk, J, rc.t0, rc.t1, rc.ez, j);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -49,8 +54,8 @@ __device__ __forceinline__ void coded_row(const CodedArgs<T, TC> &A, const coded
     const int n = rc.n;
     // cell of (piece p, slice bound j): id0[p] + (kinit + dk j) Cq + shift,
     // with the uniform part folded (wraps in 32 bits; the sum is < 2 wtot)
-    const uint32_t base = (uint32_t)kinit * A.Q.Cq + A.B.shift;
-    const int step = dk * (int)A.Q.Cq;
+    const uint32_t base = (uint32_t)kinit * K.Q.Cq + shift;
+    const int step = dk * (int)K.Q.Cq;
     uint32_t pacc = (uint32_t)rc.p0;
     int jacc = coded::code_j0(rc);
     uint32_t id[C];
@@ -59,23 +64,23 @@ __device__ __forceinline__ void coded_row(const CodedArgs<T, TC> &A, const coded
     for (int k = 0; k < C; ++k) {
         // bit i of chunk k's words is entry 64 k + i + 1: the bits below this
         // lane are the entries of the chunk up to this one
-        const uint64_t pw = A.words[rc.word + 2 * k];
-        const uint64_t kw = A.words[rc.word + 2 * k + 1];
+        const uint64_t pw = K.words[rc.word + 2 * k];
+        const uint64_t kw = K.words[rc.word + 2 * k + 1];
         const uint32_t p =
             pacc + __builtin_amdgcn_mbcnt_hi((uint32_t)(pw >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)pw, 0u));
         const int j =
             jacc + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(kw >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)kw, 0u));
         pacc += (uint32_t)__builtin_popcountll(pw);
         jacc += __builtin_popcountll(kw);
-        const double len = coded::entry_length(A.t[p], A.t[p + 1], planes[j], planes[j + 1], rc.L);
-        const TC a = A.binary ? TC(1) : TC(len);
-        const uint32_t t = A.id0[p] + base + (uint32_t)__mul24(j, step);
-        const uint32_t tw = t - A.B.wtot;
+        const double len = coded::entry_length(K.t[p], K.t[p + 1], planes[j], planes[j + 1], rc.L);
+        const TC a = K.binary ? TC(1) : TC(len);
+        const uint32_t t = K.id0[p] + base + (uint32_t)__mul24(j, step);
+        const uint32_t tw = t - wtot;
         id[k] = tw < t ? tw : t;                        // t mod wtot (t < 2 wtot < 2^32)
         av[k] = lane + 64 * k < n ? (T)a : T(0);       // masked, not branched
     }
 #pragma unroll
-    for (int k = 0; k < C; ++k) fv[k] = A.B.f[id[k]];
+    for (int k = 0; k < C; ++k) fv[k] = f[id[k]];
     T acc = T(0), amax = T(0);
 #pragma unroll
     for (int k = 0; k < C; ++k) {
@@ -85,10 +90,31 @@ __device__ __forceinline__ void coded_row(const CodedArgs<T, TC> &A, const coded
     acc = row::wave_sum(acc);
     amax = row::wave_max(amax);
     if (!(acc > T(0)) || !(amax > T(0))) return;
-    const T c = A.B.beta * (P / acc - T(1)) / amax;
+    const T c = beta * (P / acc - T(1)) / amax;
 #pragma unroll
     for (int k = 0; k < C; ++k)
-        if (lane + 64 * k < n) A.B.f[id[k]] = fv[k] * row::fmadd(c, av[k], T(1));
+        if (lane + 64 * k < n) f[id[k]] = fv[k] * row::fmadd(c, av[k], T(1));
+}
+
+// A coded row of any chunk count up to MAXC (at most 16): the straight-line
+// body of its exact count.
+template <class T, class TC, int MAXC>
+__device__ __forceinline__ void coded_row_any(const CodeTab &K, T *f, uint32_t shift, uint32_t wtot, T beta,
+                                              const coded::RayCode &rc, T P, int lane, double *planes)
+{
+    switch ((rc.n + 63) >> 6) {
+#define USPG_CODED_CASE(C)                                                                                 \
+    case C:                                                                                                \
+        if (C <= MAXC) coded_row<T, TC, (C <= MAXC ? C : 1)>(K, f, shift, wtot, beta, rc, P, lane, planes); \
+        break;
+        USPG_CODED_CASE(1) USPG_CODED_CASE(2) USPG_CODED_CASE(3) USPG_CODED_CASE(4)
+        USPG_CODED_CASE(5) USPG_CODED_CASE(6) USPG_CODED_CASE(7) USPG_CODED_CASE(8)
+        USPG_CODED_CASE(9) USPG_CODED_CASE(10) USPG_CODED_CASE(11) USPG_CODED_CASE(12)
+        USPG_CODED_CASE(13) USPG_CODED_CASE(14) USPG_CODED_CASE(15) USPG_CODED_CASE(16)
+#undef USPG_CODED_CASE
+    default:
+        break;
+    }
 }
 
 // Class position x of the band order: bands of `band` class rows, w
@@ -118,22 +144,9 @@ __global__ __launch_bounds__(kBlock) void mart_coded(CodedArgs<T, TC> A)
     for (int x = __builtin_amdgcn_readfirstlane(row::xcd_block(blockIdx.x, A.B.nblk) * kWaves + wv); x < A.B.ncls;
          x += total) {
         const int64_t r = class_ray(A, x);
-        const coded::RayCode rc = A.codes[r];
+        const coded::RayCode rc = A.K.codes[r];
         if (rc.n == 0 || rc.word < 0) continue;
-        const T P = A.B.P[r];
-        switch ((rc.n + 63) >> 6) {
-#define USPG_CODED_CASE(C)                                                                   \
-    case C:                                                                                  \
-        if (C <= MAXC) coded_row<T, TC, (C <= MAXC ? C : 1)>(A, rc, P, lane, planes[wv]);   \
-        break;
-            USPG_CODED_CASE(1) USPG_CODED_CASE(2) USPG_CODED_CASE(3) USPG_CODED_CASE(4)
-            USPG_CODED_CASE(5) USPG_CODED_CASE(6) USPG_CODED_CASE(7) USPG_CODED_CASE(8)
-            USPG_CODED_CASE(9) USPG_CODED_CASE(10) USPG_CODED_CASE(11) USPG_CODED_CASE(12)
-            USPG_CODED_CASE(13) USPG_CODED_CASE(14) USPG_CODED_CASE(15) USPG_CODED_CASE(16)
-#undef USPG_CODED_CASE
-        default:
-            break;
-        }
+        coded_row_any<T, TC, MAXC>(A.K, A.B.f, A.B.shift, A.B.wtot, A.B.beta, rc, A.B.P[r], lane, planes[wv]);
     }
 }
 
@@ -147,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void mart_explicit(CodedArgs<T, TC> A)
     const int total = A.B.nblk * kWaves;
     for (int x = row::xcd_block(blockIdx.x, A.B.nblk) * kWaves + (threadIdx.x >> 6); x < A.B.ncls; x += total) {
         const int64_t r = class_ray(A, x);
-        const coded::RayCode rc = A.codes[r];
+        const coded::RayCode rc = A.K.codes[r];
         if (rc.n == 0 || rc.word >= 0) continue;
         row::mart_row<T, TC, MAXC, NT>(A.B.f, A.B.shift, A.B.wtot, A.B.beta, A.B.co + A.B.rowptr[r], rc.n, A.B.P[r],
                                        lane);

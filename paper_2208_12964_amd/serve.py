@@ -354,4 +354,10 @@ def serve_fifo(geometry, requests, dtype=torch.float32, device="cuda:0", keep_re
         out.update({"p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99), "mean_s": sum(lat) / len(lat),
                     "req_per_s": len(done) / max(max(r.t_done for r in done) - min(r.arrival for r in done),
                                                  1e-9)})
+        # device time per geometry: one request at a time, so admission to
+        # completion is that request's whole service time
+        svc = {}
+        for r in done:
+            svc[r.key] = svc.get(r.key, 0.0) + (r.t_done - r.t_admit)
+        out["service_s_by_key"] = {f"{k[0]}x{k[1]}": v for k, v in sorted(svc.items())}
     return out
