@@ -11,8 +11,11 @@ leave as soon as their own sweeps are done.  A request's result is bit for
 bit the one ``mart`` gives for it alone.
 
 Lanes: requests are split by a lane function (default: by ring count) into
-engines on separate streams, so that small requests do not advance at the
-launch rate of the largest one.  All streams keep the default priority.
+engines, so that small requests do not advance at the launch rate of the
+largest one.  The lanes issue their calls on a stream each, or on one
+shared stream (`shared_stream=True`), where the calls of different lanes
+run one after another instead of competing for the chip.  All streams keep
+the default priority.
 
 Only host logic lives here (queues, budget, timing); every step of the
 reconstruction runs in the library.
