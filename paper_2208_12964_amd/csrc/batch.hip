@@ -21,6 +21,7 @@
 // images; neither changes the arithmetic, so every setting gives the same
 // bits, equal to running the problems one at a time.
 #include <algorithm>
+#include <cstddef>
 #include <vector>
 
 #include "mart_coded.hpp"
@@ -81,6 +82,36 @@ constexpr int kRowsStored = 0, kRowsKept = 1, kRowsCoded = 2;
 // Class rows per band of the ray order for coded problems (as in the
 // single-problem coded kernel).
 constexpr int kLockstepBand = 8;
+
+// The codes of a coefficient set are read-only while MART kernels run.
+// Read through the constant address space, a wavefront-uniform ray header
+// and its bit words load into scalar registers (mart_coded gets the same
+// from restrict-qualified arguments; here the pointers come from the
+// problem table): 83 -> 65 vector registers for the 8-chunk body.
+typedef const __attribute__((address_space(4))) uint64_t ConstU64;
+typedef const __attribute__((address_space(4))) int32_t ConstI32;
+typedef const __attribute__((address_space(4))) double ConstF64;
+
+static_assert(sizeof(coded::RayCode) == 48 && offsetof(coded::RayCode, t0) == 16 &&
+                  offsetof(coded::RayCode, ez) == 40,
+              "code_of reads the header as four int32 then four doubles");
+
+__device__ __forceinline__ coded::RayCode code_of(const coded::RayCode *codes, int64_t r)
+{
+    const coded::RayCode *g = codes + r;
+    ConstI32 *i = (ConstI32 *)g;
+    ConstF64 *d = (ConstF64 *)&g->t0;
+    coded::RayCode rc;
+    rc.n = i[0];
+    rc.p0 = i[1];
+    rc.kj = i[2];
+    rc.word = i[3];
+    rc.t0 = d[0];
+    rc.t1 = d[1];
+    rc.L = d[2];
+    rc.ez = d[3];
+    return rc;
+}
 
 // Rows of view v: the reference rows with the cell ids shifted by v Wc
 // (v < n_views <= q, so v Wc < Wtot), or the view's own kept rows (no
@@ -195,7 +226,7 @@ __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, co
     const int cu = c % S.Ku, cw = c / S.Ku;
     const int nu = (S.U - cu + S.Ku - 1) / S.Ku;
     const int nw = ((int)(S.nrays / S.U) - cw + S.Kv - 1) / S.Kv;
-    const int x = (b - wgbeg[lo]) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int x = __builtin_amdgcn_readfirstlane((b - wgbeg[lo]) * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (x >= nu * nw) return;
     int64_t r = (int64_t)(cw + (x / nu) * S.Kv) * S.U + cu + (x % nu) * S.Ku;
     if constexpr (ROWS == kRowsCoded) {
@@ -208,11 +239,11 @@ __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, co
             const int xl = x - wb * kLockstepBand * nu;
             const int h = nw - wb * kLockstepBand < kLockstepBand ? nw - wb * kLockstepBand : kLockstepBand;
             r = (int64_t)(cw + (wb * kLockstepBand + xl % h) * S.Kv) * S.U + cu + (xl / h) * S.Ku;
-            const coded::RayCode rc = S.K.codes[r];
+            const coded::RayCode rc = code_of(S.K.codes, r);
             if (rc.n == 0) return;
             if (rc.word >= 0) {   // rebuilt from the codes (same entries, same bits)
                 const uint32_t shift = (uint32_t)(((uint64_t)v * S.Wc) % S.Wtot);
-                batchk::coded_row_any<T, TC, MAXC>(S.K, D.f, shift, S.Wtot, D.beta, rc,
+                batchk::coded_row_any<T, TC, MAXC>(S.K, (const ConstU64 *)S.K.words, D.f, shift, S.Wtot, D.beta, rc,
                                                    D.P[(int64_t)v * S.nrays + r], threadIdx.x & 63,
                                                    planes[threadIdx.x >> 6]);
                 return;

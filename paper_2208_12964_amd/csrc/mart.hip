@@ -132,11 +132,11 @@ void launch_batch_n(int nch, bool nt, const BatchArgs<T, TC> &A, hipStream_t s)
 template <class T, class TC>
 void launch_coded(int nch, const CodedArgs<T, TC> &A, hipStream_t s)
 {
-    if (nch <= 2) hipLaunchKernelGGL((mart_coded<T, TC, 2>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
-    else if (nch <= 4) hipLaunchKernelGGL((mart_coded<T, TC, 4>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
-    else if (nch <= 8) hipLaunchKernelGGL((mart_coded<T, TC, 8>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
-    else if (nch <= 12) hipLaunchKernelGGL((mart_coded<T, TC, 12>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
-    else hipLaunchKernelGGL((mart_coded<T, TC, 16>), dim3(A.B.nblk), dim3(kBlock), 0, s, A);
+    if (nch <= 2) hipLaunchKernelGGL((mart_coded<T, TC, 2>), dim3(A.B.nblk), dim3(kBlock), 0, s, A, A.K.codes, A.K.words);
+    else if (nch <= 4) hipLaunchKernelGGL((mart_coded<T, TC, 4>), dim3(A.B.nblk), dim3(kBlock), 0, s, A, A.K.codes, A.K.words);
+    else if (nch <= 8) hipLaunchKernelGGL((mart_coded<T, TC, 8>), dim3(A.B.nblk), dim3(kBlock), 0, s, A, A.K.codes, A.K.words);
+    else if (nch <= 12) hipLaunchKernelGGL((mart_coded<T, TC, 12>), dim3(A.B.nblk), dim3(kBlock), 0, s, A, A.K.codes, A.K.words);
+    else hipLaunchKernelGGL((mart_coded<T, TC, 16>), dim3(A.B.nblk), dim3(kBlock), 0, s, A, A.K.codes, A.K.words);
 }
 
 template <class T, class TC, bool NT>
