@@ -33,6 +33,9 @@ struct CodedArgs {
     int band;                        // ray order: bands of `band` class rows, w fastest inside a band
 };
 
+// Two consecutive FP64 column records, 8-byte aligned.
+typedef double PieceSpan __attribute__((ext_vector_type(2), aligned(8)));
+
 // One coded row of exactly C chunks of 64 entries, kept in registers as in
 // row::row_in_registers (same masking, same reduction order).  Straight-line
 // code, so every chunk's table loads, then every gather, are issued before
@@ -72,7 +75,9 @@ __device__ __forceinline__ void coded_row(const CodeTab &K, W words, T *f, uint3
             jacc + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(kw >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)kw, 0u));
         pacc += (uint32_t)__builtin_popcountll(pw);
         jacc += __builtin_popcountll(kw);
-        const double len = coded::entry_length(K.t[p], K.t[p + 1], planes[j], planes[j + 1], rc.L);
+        // the piece's start and end (the next record's start) in one 16-byte load
+        const PieceSpan ts = *reinterpret_cast<const PieceSpan *>(K.t + p);
+        const double len = coded::entry_length(ts.x, ts.y, planes[j], planes[j + 1], rc.L);
         const TC a = K.binary ? TC(1) : TC(len);
         const uint32_t t = K.id0[p] + base + (uint32_t)__mul24(j, step);
         const uint32_t tw = t - wtot;
