@@ -4,7 +4,8 @@
 //
 //   col_count / col_fill   one thread walks one column's in-plane line
 //   ray_nwords             mask words of each ray from its entry count (scanned)
-//   ray_code               one thread codes one ray and writes its bits, or
+//   ray_code               one thread codes one ray (the rays of a column on
+//                          neighbouring lanes) and writes its bits, or
 //                          leaves it explicit
 #include <cmath>
 
@@ -70,23 +71,35 @@ __global__ __launch_bounds__(256) void ray_code(walk::TraceGeo G, CodeGeo Q, int
                                                 const uint32_t *id0, int binary, const int64_t *woff,
                                                 RayCode *codes, uint64_t *words, unsigned long long *counts)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrays) return;
-    const int n = (int)(rowptr[r + 1] - rowptr[r]);
-    RayCode rc{};
-    walk::Ray ray;
-    bool ok;
-    if (!walk::setup_ray(G, r, ray)) {
-        ok = n == 0;
-        rc.n = n;
-    } else {
-        const int u = (int)(r % G.U);
-        ok = coded::code_ray<TC>(Q, G, ray, t, id0, colptr[u], colptr[u + 1] - 1, StoredRow<TC>{co + rowptr[r]}, n,
-                                 binary != 0, rc, words + woff[r]);
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool coded_ray = false, explicit_ray = false;
+    if (tid < nrays) {
+        // the rays of one column on neighbouring lanes: they read the same
+        // column records
+        const int64_t r = walk::column_major_ray(G, tid, nrays);
+        const int n = (int)(rowptr[r + 1] - rowptr[r]);
+        RayCode rc{};
+        walk::Ray ray;
+        bool ok;
+        if (!walk::setup_ray(G, r, ray)) {
+            ok = n == 0;
+            rc.n = n;
+        } else {
+            const int u = (int)(r % G.U);
+            ok = coded::code_ray<TC>(Q, G, ray, t, id0, colptr[u], colptr[u + 1] - 1, StoredRow<TC>{co + rowptr[r]},
+                                     n, binary != 0, rc, words + woff[r]);
+        }
+        rc.word = ok ? (int32_t)woff[r] : -1;
+        codes[r] = rc;
+        coded_ray = n > 0 && ok;
+        explicit_ray = n > 0 && !ok;
     }
-    rc.word = ok ? (int32_t)woff[r] : -1;
-    codes[r] = rc;
-    if (n > 0) atomicAdd(counts + (ok ? 0 : 1), 1ull);
+    // one atomic per wavefront and count
+    const unsigned long long cm = __ballot(coded_ray), em = __ballot(explicit_ray);
+    if ((threadIdx.x & 63) == 0) {
+        if (cm) atomicAdd(counts, (unsigned long long)__popcll(cm));
+        if (em) atomicAdd(counts + 1, (unsigned long long)__popcll(em));
+    }
 }
 
 // Column records per column (scanned into colptr) and mask-word offsets per

@@ -1,7 +1,8 @@
 // Reference-view tracing on the device (Sec. III.A-B, Alg. 1).
-// One thread walks one view-0 ray in FP64 (trace_walk.hpp).  Two passes with
-// identical arithmetic: the first counts entries per ray, the second writes
-// them at the scanned offsets.
+// One thread walks one view-0 ray in FP64 (trace_walk.hpp), the rays of a
+// detector column on neighbouring threads.  Two passes with identical
+// arithmetic: the first counts entries per ray, the second writes them at
+// the scanned offsets.
 #include <cmath>
 
 #include "trace_walk.hpp"
@@ -18,8 +19,9 @@ using walk::setup_ray;
 
 __global__ __launch_bounds__(256) void trace_count(TraceGeo G, int64_t nrays, uint32_t *cnt)
 {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrays) return;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= nrays) return;
+    const int64_t r = walk::column_major_ray(G, tid, nrays);
     Ray ray;
     uint32_t n = 0;
     if (setup_ray(G, r, ray)) {
@@ -40,8 +42,9 @@ template <class TC>
 __global__ __launch_bounds__(256) void trace_fill(TraceGeo G, int64_t nrays, const int64_t *rowptr,
                                                   uint32_t *ids, TC *a, int binary)
 {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrays) return;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= nrays) return;
+    const int64_t r = walk::column_major_ray(G, tid, nrays);
     Ray ray;
     if (!setup_ray(G, r, ray)) return;
     RowSink<true, TC> sink;

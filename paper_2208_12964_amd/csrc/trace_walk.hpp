@@ -61,6 +61,17 @@ struct TraceGeo {
     double eps;
 };
 
+// Ray handled by thread `tid` of a per-ray launch: the rays of one detector
+// column (same u, consecutive rows) take neighbouring threads, so the lanes
+// of a wavefront share their column's in-plane walk (same ring and sector
+// steps, same table entries) and differ only in their slice steps.  A
+// bijection of [0, U V); any other ray count keeps the identity.
+USPG_HD inline int64_t column_major_ray(const TraceGeo &G, int64_t tid, int64_t nrays)
+{
+    if (G.U <= 0 || G.V <= 1 || nrays != (int64_t)G.U * G.V) return tid;
+    return (tid % G.V) * G.U + tid / G.V;
+}
+
 // Device (wedge-major, ring-group blocked) image layout.
 //
 // With q view steps per turn, ring i holds k_i = n_g(i) / q sectors per

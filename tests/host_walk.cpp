@@ -36,6 +36,16 @@ struct Capture {
 
 extern "C" {
 
+// Ray of thread tid in the per-ray launches (column_major_ray) for a U x V
+// detector.
+int64_t hw_column_major(int U, int V, int64_t tid)
+{
+    TraceGeo G{};
+    G.U = U;
+    G.V = V;
+    return column_major_ray(G, tid, (int64_t)U * V);
+}
+
 // Grid and scan of the walk; q = view steps per turn (must divide every ng);
 // grp = rings per group of the device layout.
 int hw_setup(int nr, int nz, double R, double H, const int32_t *ng, int q, int geom, int is3d, int U,

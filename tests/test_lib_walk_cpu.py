@@ -38,6 +38,8 @@ def hw():
     L.hw_columns.restype = C.c_int64
     L.hw_column_gaps.restype = C.c_int64
     L.hw_code_ray.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    L.hw_column_major.argtypes = [C.c_int, C.c_int, C.c_int64]
+    L.hw_column_major.restype = C.c_int64
     return L
 
 
@@ -208,3 +210,17 @@ def test_coded_rows_rebuild_the_walk(hw, name, step):
             assert np.array_equal(ids[:n].astype(np.int64), c2)
             assert np.array_equal(lens[:n], l2.astype(np.float32))
     assert coded > 0
+
+
+@pytest.mark.parametrize("U,V", [(512, 512), (7, 5), (20, 1), (1, 9)])
+def test_column_major_threads_cover_every_ray_once(hw, U, V):
+    # the per-ray launches give the rays of one detector column to
+    # neighbouring threads: thread -> ray must be a bijection of [0, U V),
+    # with ray = v U + u and thread = u V + v
+    rays = np.array([hw.hw_column_major(U, V, t) for t in range(U * V)], dtype=np.int64)
+    assert np.array_equal(np.sort(rays), np.arange(U * V))
+    t = np.arange(U * V)
+    if V > 1:
+        assert np.array_equal(rays, (t % V) * U + t // V)
+    else:
+        assert np.array_equal(rays, t)
