@@ -238,6 +238,8 @@ static int fill_rows(uspg_coeffs *c, Arena &a, hipStream_t s)
     if ((rc = trace_fill_rows(c, s)) != USPG_OK || (rc = colour_reference_view(c, s)) != USPG_OK) return rc;
     if (c->want_codes && (rc = code_fill(c, s)) != USPG_OK) return rc;
     c->pend_cnt.release();
+    c->pend_colptr.release();
+    c->pend_woff.release();
     return USPG_OK;
 }
 

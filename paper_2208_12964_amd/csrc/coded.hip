@@ -138,15 +138,22 @@ int fill_typed(uspg_coeffs *c, hipStream_t s)
         !c->d_words.p)
         return fail(USPG_E_INTERNAL, "coded rows: rows or code buffers not on the device");
     DevBuf woff, counts;
-    if ((rc = woff.alloc(sizeof(int64_t) * (nrays + 1))) != USPG_OK) return rc;
     if ((rc = counts.alloc(2 * sizeof(unsigned long long))) != USPG_OK) return rc;
-    if ((rc = code_offsets(c, c->d_colptr.as<int64_t>(), woff.as<int64_t>(), s)) != USPG_OK) return rc;
+    if (c->pend_colptr.p && c->pend_woff.p) {
+        // the offsets of the count pass
+        USPG_HIP(hipMemcpyAsync(c->d_colptr.p, c->pend_colptr.p, sizeof(int64_t) * (U + 1), hipMemcpyDeviceToDevice,
+                                s));
+    } else {
+        if ((rc = woff.alloc(sizeof(int64_t) * (nrays + 1))) != USPG_OK) return rc;
+        if ((rc = code_offsets(c, c->d_colptr.as<int64_t>(), woff.as<int64_t>(), s)) != USPG_OK) return rc;
+    }
+    const int64_t *wo = woff.p ? woff.as<int64_t>() : c->pend_woff.as<int64_t>();
     hipLaunchKernelGGL(col_fill, dim3((U + 255) / 256), dim3(256), 0, s, G, c->d_colptr.as<int64_t>(),
                        c->d_colt.as<double>(), c->d_colid.as<uint32_t>());
     USPG_HIP(hipMemsetAsync(counts.p, 0, 2 * sizeof(unsigned long long), s));
     hipLaunchKernelGGL(ray_code<TC>, dim3((unsigned)((nrays + 255) / 256)), dim3(256), 0, s, G, Q, nrays,
                        c->rowptr.as<int64_t>(), c->coef.as<Coef<TC>>(), c->d_colptr.as<int64_t>(),
-                       c->d_colt.as<double>(), c->d_colid.as<uint32_t>(), binary, woff.as<int64_t>(),
+                       c->d_colt.as<double>(), c->d_colid.as<uint32_t>(), binary, wo,
                        c->d_codes.as<RayCode>(), c->d_words.as<uint64_t>(), counts.as<unsigned long long>());
     USPG_HIP(hipGetLastError());
     unsigned long long hc[2] = {0, 0};
@@ -165,7 +172,8 @@ int code_count(uspg_coeffs *c, hipStream_t s)
     const int U = c->scan.det_u;
     const int64_t nrays = c->nrays;
     int rc;
-    DevBuf colptr, woff;
+    // kept in the handle for the fill, which then needs no second column walk
+    DevBuf &colptr = c->pend_colptr, &woff = c->pend_woff;
     if ((rc = colptr.alloc(sizeof(int64_t) * (U + 1))) != USPG_OK) return rc;
     if ((rc = woff.alloc(sizeof(int64_t) * (nrays + 1))) != USPG_OK) return rc;
     if ((rc = code_offsets(c, colptr.as<int64_t>(), woff.as<int64_t>(), s)) != USPG_OK) return rc;

@@ -147,6 +147,8 @@ struct uspg_coeffs {
     bool want_codes = false;
     size_t ws_needed = 0;
     uspg::DevBuf pend_cnt;        // uint32 [nrays + 1]: entries per ray (library memory, until the fill)
+    uspg::DevBuf pend_colptr;     // int64 [det_u + 1]: coded rows, column record offsets (until the fill)
+    uspg::DevBuf pend_woff;       // int64 [nrays + 1]: coded rows, mask word offsets (until the fill)
     int64_t pend_nrec = 0, pend_nwords = 0;
 };
 
