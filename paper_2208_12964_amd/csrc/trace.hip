@@ -38,9 +38,11 @@ __global__ __launch_bounds__(256) void trace_count(TraceGeo G, int64_t nrays, ui
     cnt[r] = n;
 }
 
+// Writes each row's (id, coefficient) pairs straight into the coefficient
+// array.
 template <class TC>
-__global__ __launch_bounds__(256) void trace_fill(TraceGeo G, int64_t nrays, const int64_t *rowptr,
-                                                  uint32_t *ids, TC *a, int binary)
+__global__ __launch_bounds__(256) void trace_fill(TraceGeo G, int64_t nrays, const int64_t *rowptr, Coef<TC> *co,
+                                                  int binary)
 {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= nrays) return;
@@ -49,23 +51,14 @@ __global__ __launch_bounds__(256) void trace_fill(TraceGeo G, int64_t nrays, con
     if (!setup_ray(G, r, ray)) return;
     RowSink<true, TC> sink;
     sink.base = rowptr[r];
-    sink.ids = ids;
-    sink.a = a;
+    sink.ids = &co[0].id;
+    sink.a = &co[0].a;
+    sink.ids_stride = sizeof(Coef<TC>) / sizeof(uint32_t);
+    sink.a_stride = sizeof(Coef<TC>) / sizeof(TC);
     sink.binary = binary != 0;
     sink.eps = G.eps;
     Walker<RowSink<true, TC>> w(G, ray, sink);
     w.run();
-}
-
-template <class TC>
-__global__ __launch_bounds__(256) void interleave_coef(const uint32_t *ids, const TC *a, int64_t n, Coef<TC> *out)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    Coef<TC> e{};
-    e.id = ids[i];
-    e.a = a[i];
-    out[i] = e;
 }
 
 __global__ void row_lengths_max(const uint32_t *cnt, int64_t n, unsigned int *mx)
@@ -136,33 +129,19 @@ int trace_fill_rows(uspg_coeffs *c, hipStream_t s)
     const TraceGeo G = trace_geo(c);
     if (!G.kq || !G.hq || !c->pend_cnt.p || !c->rowptr.p || !c->coef.p)
         return fail(USPG_E_INTERNAL, "trace: tables, counts or rows not on the device");
-    const int64_t nrays = c->nrays, nnz = c->nnz;
+    const int64_t nrays = c->nrays;
     const unsigned blocks = (unsigned)((nrays + 255) / 256);
     int rc = USPG_OK;
     do {
         if ((rc = exclusive_scan_u32_to_i64(c->pend_cnt.as<uint32_t>(), c->rowptr.as<int64_t>(), nrays, s)) != USPG_OK)
             break;
-        // the walk writes ids and coefficients as two arrays, then they are
-        // interleaved into the (id, coefficient) pairs the kernels read
-        const bool f64 = sc.coeff_dtype == USPG_F64;
-        const size_t asz = f64 ? sizeof(double) : sizeof(float);
-        const int64_t n1 = nnz > 0 ? nnz : 1;
-        DevBuf ids, a;
-        if ((rc = ids.alloc(sizeof(uint32_t) * n1)) != USPG_OK) break;
-        if ((rc = a.alloc(asz * n1)) != USPG_OK) break;
-        int binary = sc.weights == USPG_WEIGHTS_BINARY;
-        const unsigned eb = (unsigned)((n1 + 255) / 256);
-        if (f64) {
-            hipLaunchKernelGGL(trace_fill<double>, dim3(blocks), dim3(256), 0, s, G, nrays,
-                               c->rowptr.as<int64_t>(), ids.as<uint32_t>(), a.as<double>(), binary);
-            hipLaunchKernelGGL(interleave_coef<double>, dim3(eb), dim3(256), 0, s, ids.as<uint32_t>(), a.as<double>(),
-                               nnz, c->coef.as<Coef<double>>());
-        } else {
-            hipLaunchKernelGGL(trace_fill<float>, dim3(blocks), dim3(256), 0, s, G, nrays,
-                               c->rowptr.as<int64_t>(), ids.as<uint32_t>(), a.as<float>(), binary);
-            hipLaunchKernelGGL(interleave_coef<float>, dim3(eb), dim3(256), 0, s, ids.as<uint32_t>(), a.as<float>(),
-                               nnz, c->coef.as<Coef<float>>());
-        }
+        const int binary = sc.weights == USPG_WEIGHTS_BINARY;
+        if (sc.coeff_dtype == USPG_F64)
+            hipLaunchKernelGGL(trace_fill<double>, dim3(blocks), dim3(256), 0, s, G, nrays, c->rowptr.as<int64_t>(),
+                               c->coef.as<Coef<double>>(), binary);
+        else
+            hipLaunchKernelGGL(trace_fill<float>, dim3(blocks), dim3(256), 0, s, G, nrays, c->rowptr.as<int64_t>(),
+                               c->coef.as<Coef<float>>(), binary);
         const bool launched = hipGetLastError() == hipSuccess;
         const bool synced = hipStreamSynchronize(s) == hipSuccess;
         if (!launched) { rc = fail(USPG_E_HIP, "trace_fill launch failed"); break; }

@@ -153,12 +153,16 @@ struct RowSink {
     TC *a;
     bool binary;
     double eps;
+    // element strides of ids and a (in their own units): 1 for two plain
+    // arrays, or the pair size when both point into an array of (id, a)
+    // pairs
+    int64_t ids_stride = 1, a_stride = 1;
 
     USPG_HD void flush(const Entry &e)
     {
         if (WRITE) {
-            ids[base + e.slot] = e.id;
-            a[base + e.slot] = binary ? TC(1) : TC(e.len);
+            ids[(base + e.slot) * ids_stride] = e.id;
+            a[(base + e.slot) * a_stride] = binary ? TC(1) : TC(e.len);
         }
     }
     USPG_HD void emit(uint32_t id, double len)
