@@ -83,11 +83,11 @@ def parse():
     ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=120.0, help="serve: arrival window (s)")
     ap.add_argument("--budget-gib", type=float, default=16.0, help="serve: admission budget (GiB)")
-    ap.add_argument("--steps-per-call", type=int, default=128, help="serve: engine steps per call")
+    ap.add_argument("--steps-per-call", type=int, default=512, help="serve: engine steps per call")
     ap.add_argument("--lanes", default="split", choices=["rings", "split", "one"],
                     help="serve: one engine per ring count; the 256-ring requests (whose steps fill the "
                          "chip alone) in one engine and the rest in engine 0; or a single engine")
-    ap.add_argument("--slots", default="256:2,0:40",
+    ap.add_argument("--slots", default="256:1,0:40",
                     help="serve: slots per lane as lane:count pairs (lane = ring count with --lanes rings; "
                          "256 and 0 with --lanes split; 0 with --lanes one)")
     ap.add_argument("--fifo", action="store_true", help="serve: also run the one-at-a-time baseline")
