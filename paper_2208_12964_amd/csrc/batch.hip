@@ -83,11 +83,12 @@ constexpr int kRowsStored = 0, kRowsKept = 1, kRowsCoded = 2;
 // single-problem coded kernel).
 constexpr int kLockstepBand = 8;
 
-// The codes of a coefficient set are read-only while MART kernels run.
-// Read through the constant address space, a wavefront-uniform ray header
-// and its bit words load into scalar registers (mart_coded gets the same
-// from restrict-qualified arguments; here the pointers come from the
-// problem table): 83 -> 65 vector registers for the 8-chunk body.
+// The codes of a coefficient set and the projections are read-only while
+// MART kernels run.  Read through the constant address space, a
+// wavefront-uniform ray header, its bit words and its measurement load into
+// scalar registers (mart_coded gets the same from restrict-qualified
+// arguments; here the pointers come from the problem table): 83 -> 65
+// vector registers for the 8-chunk body.
 typedef const __attribute__((address_space(4))) uint64_t ConstU64;
 typedef const __attribute__((address_space(4))) int32_t ConstI32;
 typedef const __attribute__((address_space(4))) double ConstF64;
@@ -243,9 +244,9 @@ __global__ __launch_bounds__(256) void mart_lockstep(const ProblemStatic *st, co
             if (rc.n == 0) return;
             if (rc.word >= 0) {   // rebuilt from the codes (same entries, same bits)
                 const uint32_t shift = (uint32_t)(((uint64_t)v * S.Wc) % S.Wtot);
+                const T P = ((const __attribute__((address_space(4))) T *)D.P)[(int64_t)v * S.nrays + r];
                 batchk::coded_row_any<T, TC, MAXC>(S.K, (const ConstU64 *)S.K.words, D.f, shift, S.Wtot, D.beta, rc,
-                                                   D.P[(int64_t)v * S.nrays + r], threadIdx.x & 63,
-                                                   planes[threadIdx.x >> 6]);
+                                                   P, threadIdx.x & 63, planes[threadIdx.x >> 6]);
                 return;
             }
         }

@@ -132,11 +132,14 @@ void launch_batch_n(int nch, bool nt, const BatchArgs<T, TC> &A, hipStream_t s)
 template <class T, class TC>
 void launch_coded(int nch, const CodedArgs<T, TC> &A, hipStream_t s)
 {
-    if (nch <= 2) hipLaunchKernelGGL((mart_coded<T, TC, 2>), dim3(A.B.nblk), dim3(kBlock), 0, s, A, A.K.codes, A.K.words);
-    else if (nch <= 4) hipLaunchKernelGGL((mart_coded<T, TC, 4>), dim3(A.B.nblk), dim3(kBlock), 0, s, A, A.K.codes, A.K.words);
-    else if (nch <= 8) hipLaunchKernelGGL((mart_coded<T, TC, 8>), dim3(A.B.nblk), dim3(kBlock), 0, s, A, A.K.codes, A.K.words);
-    else if (nch <= 12) hipLaunchKernelGGL((mart_coded<T, TC, 12>), dim3(A.B.nblk), dim3(kBlock), 0, s, A, A.K.codes, A.K.words);
-    else hipLaunchKernelGGL((mart_coded<T, TC, 16>), dim3(A.B.nblk), dim3(kBlock), 0, s, A, A.K.codes, A.K.words);
+    const coded::RayCode *codes = A.K.codes;
+    const uint64_t *words = A.K.words;
+    const dim3 g(A.B.nblk), blk(kBlock);
+    if (nch <= 2) hipLaunchKernelGGL((mart_coded<T, TC, 2>), g, blk, 0, s, A, codes, words, A.B.P);
+    else if (nch <= 4) hipLaunchKernelGGL((mart_coded<T, TC, 4>), g, blk, 0, s, A, codes, words, A.B.P);
+    else if (nch <= 8) hipLaunchKernelGGL((mart_coded<T, TC, 8>), g, blk, 0, s, A, codes, words, A.B.P);
+    else if (nch <= 12) hipLaunchKernelGGL((mart_coded<T, TC, 12>), g, blk, 0, s, A, codes, words, A.B.P);
+    else hipLaunchKernelGGL((mart_coded<T, TC, 16>), g, blk, 0, s, A, codes, words, A.B.P);
 }
 
 template <class T, class TC, bool NT>
