@@ -41,11 +41,12 @@ using batchk::mart_coded;
 using batchk::mart_explicit;
 constexpr int kWaves = batchk::kWaves;
 constexpr int kBlock = batchk::kBlock;
-// Grid cap of the batch kernel, in workgroups per compute unit: measured on
+// Grid cap of the batch kernels, in workgroups per compute unit: measured on
 // the 256-ring cone (43,690 rays per class), 16 per CU (4,096 on 256 CUs)
-// gave 122 us per batch against 135 us for one wavefront per ray; 8, 12,
-// 20, 24 and 32 per CU gave 128-150 us.  Classes of fewer rays are not
-// capped.
+// gave 122 us per batch against 135 us for one wavefront per ray with
+// stored rows, 8, 12, 20, 24 and 32 per CU 128-150 us; with coded rows 16
+// per CU gives 79 us, 8 / 12 / 24 per CU 87 / 86 / 94 us.  Classes of fewer
+// rays are not capped.
 constexpr int kBlocksPerCU = 16;
 
 int grid_cap()
