@@ -245,6 +245,9 @@ void uspg_free_coeffs(uspg_coeffs *c);
  * image: device [n_cells] in the paper's numbering; read as f0 (> 0) and
  *        overwritten with the result.
  * work:  device scratch of at least uspg_mart_workspace_bytes() bytes.
+ *        proj, image, work and the coefficient set's work space must not
+ *        overlap (the kernels read proj and the codes as read-only data
+ *        that no store of theirs can alias).
  * tol:   0 runs exactly n_sweeps sweeps with no host synchronisation; tol > 0
  *        stops after the first sweep with max_j |f_new - f_old| / f_old <= tol
  *        (eq. 19) and synchronises the stream once per sweep.
