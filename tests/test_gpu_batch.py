@@ -150,3 +150,29 @@ def test_batch_configuration_sizes_equal_oracle(U):
         err = np.max(np.abs(f - f_ref)) / np.max(np.abs(f_ref))
         print(f"{w.name} (Nr {w.n_rings}): err_inf {err:.2e}")
         assert err <= 1e-4, w.name
+
+
+def test_cone_batch_in_cache_sized_groups_equal_alone(U):
+    # ten 128-ring, 32-view cone requests: the image lines one step touches
+    # (about 21 MB per request) outgrow the last-level cache together, so the
+    # lockstep batch runs them in two groups, the second from the step the
+    # first ends; every result equals the request alone bit for bit
+    dev = torch.device("cuda:0")
+    ws = [synth.serve_request(40 + k, 128, 32, 2) for k in range(10)]
+    print("case grouped cone batch", len(ws), flush=True)
+    g = U.Grid.from_workload(ws[0])
+    co = U.Coeffs.from_workload(g, ws[0])
+    projs = [synth.make_projections_torch(w, dev, torch.float32).reshape(-1).contiguous() for w in ws]
+    alone = []
+    for proj, w in zip(projs, ws):
+        img = torch.ones(g.n_cells, device=dev)
+        U.mart(co, proj, img, w.sweeps, w.beta)
+        alone.append(img)
+    b = U.Batch([co] * len(ws))
+    b.set("lockstep", 256)
+    imgs = [torch.ones(g.n_cells, device=dev) for _ in ws]
+    b.run(projs, imgs, [w.sweeps for w in ws], [w.beta for w in ws])
+    torch.cuda.synchronize()
+    for k, (a, m) in enumerate(zip(alone, imgs)):
+        assert torch.equal(a, m), k
+    b.close()
