@@ -67,11 +67,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cone-256r-32v-hc")
-    ap.add_argument("--mode", default="single", choices=["single", "batch2d", "serve", "paper", "slabs"],
+    ap.add_argument("--mode", default="single",
+                    choices=["single", "batch2d", "conebatch", "serve", "paper", "slabs"],
                     help="single: the 256-ring cone path (default); batch2d: 64 mixed 2D slices "
-                         "one at a time vs one persistent launch; serve: the request loop; paper: the "
-                         "paper's Table 1 scans with its literal segment scheme and image quality; "
-                         "slabs: the same solve split into z-slabs (the multi-device layout) on one GPU")
+                         "one at a time vs one persistent launch; conebatch: n copies of a cone-beam "
+                         "serving request, one at a time vs one lockstep batch; serve: the request "
+                         "loop; paper: the paper's Table 1 scans with its literal segment scheme and "
+                         "image quality; slabs: the same solve split into z-slabs (the multi-device "
+                         "layout) on one GPU")
     ap.add_argument("--slabs", type=int, default=8, help="slabs: number of z-slabs")
     ap.add_argument("--rows", default="coded", choices=["coded", "stored"],
                     help="cone-beam rows: coded (rebuilt per column, the default) or stored (id, coefficient) pairs")
@@ -475,8 +478,71 @@ def bench_slabs(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_conebatch(args):
+    """n copies (1, 2, 4, 8, 16) of cone-beam serving requests (128 rings,
+    32 and 8 views; 64 rings, 32 and 8 views; 3 sweeps, one phantom each):
+    one mart() after another vs one lockstep batch, ray-cell updates/s of
+    each; the batch results are checked bit for bit against the requests
+    alone.  value = updates/s of sixteen 128-ring, 32-view requests batched."""
+    import torch
+
+    import paper_2208_12964_amd as U
+    import synth
+
+    dev = torch.device("cuda:0")
+    rows, head = [], None
+    for nr, p in ((128, 32), (128, 8), (64, 32), (64, 8)):
+        ws = [synth.serve_request(100 + k, nr, p, 3) for k in range(16)]
+        g = U.Grid.from_workload(ws[0])
+        co = U.Coeffs.from_workload(g, ws[0])
+        projs = [synth.make_projections_torch(w, dev, torch.float32).reshape(-1).contiguous() for w in ws]
+        per = ws[0].sweeps * ws[0].n_views * co.nnz
+
+        def alone(n):
+            imgs = [torch.ones(g.n_cells, device=dev) for _ in range(n)]
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for im, pr, w in zip(imgs, projs, ws):
+                U.mart(co, pr, im, w.sweeps, w.beta)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t, imgs
+
+        alone(1)
+        for n in (1, 2, 4, 8, 16):
+            t_a, ref = min((alone(n) for _ in range(2)), key=lambda x: x[0])
+            b = U.Batch([co] * n)
+            b.set("lockstep", 256)
+            works = b.work_buffers(dev)
+            best, imgs = None, None
+            for _ in range(3):
+                imgs = [torch.ones(g.n_cells, device=dev) for _ in range(n)]
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                b.run(projs[:n], imgs, [w.sweeps for w in ws[:n]], [w.beta for w in ws[:n]], works=works)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+                best = dt if best is None else min(best, dt)
+            same = all(torch.equal(a, m) for a, m in zip(ref, imgs))
+            b.close()
+            row = {"rings": nr, "views": p, "n": n, "alone_updates_per_s": n * per / t_a,
+                   "batched_updates_per_s": n * per / best, "batched_ms": best * 1e3, "bitwise_equal": same}
+            rows.append(row)
+            if nr == 128 and p == 32 and n == 16:
+                head = row
+            print(f"conebatch: {nr} rings, {p} views, n={n}: alone {row['alone_updates_per_s'] / 1e9:.1f} G/s, "
+                  f"batched {row['batched_updates_per_s'] / 1e9:.1f} G/s, equal {same}", file=sys.stderr, flush=True)
+    out = {"metric": "ray-cell updates/s of 16 batched 128-ring, 32-view cone-beam requests",
+           "value": head["batched_updates_per_s"], "unit": "updates/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+           "ms_per_step": head["batched_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic", "config": {"workload": "conebatch", "sweeps": 3},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.mode == "conebatch" and args.gpus == 1:
+        return bench_conebatch(args)
     if args.mode == "slabs" and args.gpus == 1:
         return bench_slabs(args)
     if args.mode == "paper" and args.gpus == 1:
