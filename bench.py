@@ -611,6 +611,10 @@ def main():
     mart_each = [r[0][1].elapsed_time(r[0][2]) for r in rec]
     mart_ms = np.mean(mart_each)
     remap_ms = np.mean([r[0][2].elapsed_time(r[0][3]) for r in rec])
+    solve_each = sorted(r[0][0].elapsed_time(r[0][3]) for r in rec)
+
+    def solve_pct(q):
+        return float(solve_each[max(0, min(len(solve_each) - 1, -(-q * len(solve_each) // 100) - 1))])
     n_launch = w.sweeps * w.n_views * lattice[0] * lattice[1]
     assert batch_launches == n_launch * args.steps
     per_launch_s = batch_ms * 1e-3 / batch_launches
@@ -633,6 +637,9 @@ def main():
         "phases_ms": {"build": build_ms, "mart": mart_ms, "remap": remap_ms},
         "mart_ms_over_steps": {"median": float(np.median(mart_each)), "min": float(np.min(mart_each)),
                                "max": float(np.max(mart_each))},
+        # one solve (build, sweeps, remap) per step, device time; nearest-rank
+        # percentiles over the timed steps
+        "solve_latency_ms": {"p50": solve_pct(50), "p99": solve_pct(99), "n": len(solve_each)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
