@@ -344,8 +344,12 @@ int uspg_batch_info(const uspg_batch *b, int32_t *mode, int32_t *block_threads, 
  * work[i] device scratch of work_bytes[i] >= uspg_mart_workspace_bytes(coeffs
  * [i], dtype, 0)), per-problem sweep counts and relaxation.  Fixed sweep
  * counts only (no stopping rule).  Asynchronous on `stream` (a first run,
- * or one with a new step count, captures the lockstep graph first).
- * The caller must not run the same batch on two streams at once. */
+ * or one with a new step count or grouping, captures the lockstep graph
+ * first).  In lockstep mode, problems whose image lines touched per step
+ * would together outgrow the last-level cache run in successive groups (in
+ * their order, each group from the step where the previous one ends); the
+ * results do not depend on the grouping.  The caller must not run the same
+ * batch on two streams at once. */
 int mart_run_batch(uspg_batch *b, const void *const *proj, void *const *image, void *const *work,
                    const size_t *work_bytes, const int32_t *n_sweeps, const double *beta, void *stream);
 
